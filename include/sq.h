@@ -1,0 +1,168 @@
+/*
+ * sq.h -- C ABI of libsq: the spectral-quadrature (SQ) density/energy step of
+ * SQDFT (arXiv 1708.07913) on one AMD MI355X (gfx950) GPU.
+ *
+ * The library computes, for every node q of a periodic finite-difference grid,
+ * the Clenshaw-Curtis SQ electron density and energies of the infinite crystal
+ * whose unit cell is the cubic domain (Sec. 3, infinite-cell SQ):
+ *
+ *   bounds    l_min, l_max of the nodal Hamiltonian H_q by Lanczos  (Sec. 3.2)
+ *   moments   rho_q^j = e_q^T T_j(Hhat_q) e_q, j = 0..n_pl           (Sec. 3.2,
+ *             Chebyshev three-term recurrence + product property)
+ *   Fermi     mu with 2 sum_q sum_j c_q^j(mu) rho_q^j = N_e (Brent)  (Sec. 3.2)
+ *   density   rho_q = (2/h^3) sum_j c_q^j rho_q^j                    (Sec. 3.2)
+ *   energies  E_band = 2 sum (chi c + zeta d) rho^j,
+ *             E_ent  = 2 sigma sum e rho^j                           (Sec. 3.3)
+ *
+ * H_q is the restriction to the cube of side 2 R_cut around q (the region of
+ * influence, Sec. 3.1) of H = -1/2 lap_h + V_eff + sum_I gamma_I h^3 p_I p_I^T:
+ * central FD Laplacian of order fd_order (Sec. 3.1), V_eff sampled at the
+ * periodic image of each cube point, one s-type Kleinman-Bylander projector per
+ * atom image (every lattice image is a separate projector), stencil legs that
+ * leave the cube dropped (zero Dirichlet at infinity).
+ *
+ * Units: lengths in Bohr, energies and kT in Hartree.
+ * Grid: n = round(cell / h) nodes per axis, h_eff = cell / n, node (i,j,k) at
+ * h_eff (i,j,k), flat index i + n (j + n k).  Cube half-width
+ * m = floor(R_cut / h_eff + 1/2), N_s = (2m+1)^3.
+ *
+ * Memory: every device buffer is owned by the caller (e.g. allocated through
+ * PyTorch) and borrowed by the library for the duration of a call; the
+ * library never allocates or frees device memory.  Pointers marked (device)
+ * must be device pointers on the current HIP device; pointers marked (host)
+ * are ordinary host memory.
+ *
+ * Streams: every call takes the caller's hipStream_t as `void *stream` (NULL
+ * = the null stream) and enqueues its kernels there.  Calls that return host
+ * scalars (or report device-side errors) synchronise that stream before
+ * returning.
+ *
+ * Errors: every call returns an sq_status; no C++ exception crosses the ABI.
+ * On failure sq_last_error() returns a message for the calling thread.
+ *
+ * Call order per V_eff: sq_setup -> sq_query -> sq_bind -> (sq_spectral_bounds
+ * | sq_set_bounds) -> sq_moments -> sq_fermi_level -> sq_density_energy.
+ * Out-of-order calls return SQ_ESTATE.  sq_update_veff invalidates bounds.
+ */
+#ifndef SQ_H
+#define SQ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sq_ctx sq_ctx;
+
+typedef enum {
+    SQ_OK = 0,
+    SQ_EINVAL = -1,      /* invalid argument */
+    SQ_ENOMEM = -2,      /* workspace too small / host allocation failed */
+    SQ_EDEVICE = -3,     /* HIP runtime error or kernel fault */
+    SQ_ESTATE = -4,      /* call out of order */
+    SQ_ENOCONV = -5,     /* Fermi-level search did not converge / no bracket */
+    SQ_EBOUNDS = -6,     /* a moment left [-1, 1]: spectral bounds too tight */
+    SQ_ECAPACITY = -7    /* a per-node table exceeded its compiled capacity */
+} sq_status;
+
+enum { SQ_FP64 = 0, SQ_FP32_MIXED = 1 };
+
+typedef struct sq_options {
+    /* SQ_FP64: everything in FP64.  SQ_FP32_MIXED: recurrence vectors, potential
+     * window and stencil pair sums in FP32, every accumulation (stencil sum,
+     * projector dots, moments), the Lanczos bounds, coefficients, Fermi solve
+     * and energies in FP64. */
+    int precision;
+    int n_lanczos;       /* Lanczos steps per node, 1..256 (default 50) */
+    double margin;       /* zeta = (1 + margin)(l_max - l_min)/2 (default 0.05) */
+    double mu_xtol;      /* Brent stop: bracket half-width (Ha), default 1e-14 */
+    double ne_rtol;      /* Brent stop: |N(mu) - N_e| <= ne_rtol * N_e, default 1e-13 */
+    int max_brent;       /* Brent iteration cap (default 200) */
+    int workgroups;      /* persistent workgroups for the recurrence kernels (0 = auto) */
+} sq_options;
+
+/* Fill *opt with the defaults above. */
+void sq_default_options(sq_options *opt);
+
+/*
+ * Create a context for one snapshot (Sec. 3.1 problem statement).
+ *   cell      cubic cell edge L (> 0)
+ *   h         requested mesh size (> 0); refitted to L / round(L / h)
+ *   fd_order  even order 2 n_o of the central FD Laplacian, 2..12
+ *   rcut      R_cut: half-side of the cubic region of influence; m >= 1
+ *   npl       quadrature order n_pl, a multiple of 4 in [4, 1000]
+ *   kT        smearing sigma (Ha, > 0)
+ *   natom     number of atoms (>= 0)
+ *   atom_xyz  (host) natom x 3 Cartesian positions, any real values (images
+ *             are taken care of)
+ *   kb        (host) natom x 3: projector Gaussian width s, cut radius r_c and
+ *             energy gamma; chi(r) = exp(-r^2/(2 s^2)) for r <= r_c, normalised
+ *             so that h^3 sum chi^2 = 1 over the full sphere; may be NULL only
+ *             if natom == 0
+ *   opt       (host) options or NULL for the defaults
+ * Host inputs are copied.  On success *ctx owns host tables only.
+ */
+int sq_setup(sq_ctx **ctx, double cell, double h, int fd_order, double rcut, int npl,
+             double kT, int natom, const double *atom_xyz, const double *kb,
+             const sq_options *opt);
+
+/* Sizes of a context: grid points per axis n, cube half-width m, node count
+ * n^3 and the device workspace (bytes) that sq_bind needs.  Any out pointer
+ * may be NULL. */
+int sq_query(const sq_ctx *ctx, int *n, int *m, long long *n_nodes, size_t *workspace_bytes);
+
+/* Bind a caller-allocated device workspace (>= workspace_bytes, 256-byte
+ * aligned) and the effective potential veff (device, n^3 FP64, flat index
+ * i + n (j + n k)); uploads the projector tables.  veff is borrowed until the
+ * next sq_bind / sq_update_veff or sq_destroy.  Synchronises `stream`. */
+int sq_bind(sq_ctx *ctx, void *workspace, size_t bytes, const double *veff, void *stream);
+
+/* Replace V_eff (device, n^3 FP64) for the next SCF iteration; bounds must be
+ * recomputed or re-injected afterwards. */
+int sq_update_veff(sq_ctx *ctx, const double *veff, void *stream);
+
+/* Spectral bounds of every H_q by n_lanczos Lanczos steps (Sec. 3.2): writes
+ * l_min, l_max (device, N_d FP64 each; either may be NULL) and keeps
+ * chi_q = (l_max + l_min)/2, zeta_q = (1 + margin)(l_max - l_min)/2 in the
+ * workspace.  Synchronises `stream`. */
+int sq_spectral_bounds(sq_ctx *ctx, double *lmin, double *lmax, void *stream);
+
+/* Inject bounds instead of computing them (device, N_d FP64 each): the same
+ * chi/zeta rule is applied.  Used to compare two implementations of the
+ * recurrence on identical bounds. */
+int sq_set_bounds(sq_ctx *ctx, const double *lmin, const double *lmax, void *stream);
+
+/* Chebyshev moments (Sec. 3.2): moments (device, N_d x (n_pl + 1) FP64,
+ * row-major by node) receives rho_q^j = e_q^T T_j(Hhat_q) e_q.  Columns
+ * 0..n_pl/2 come from the recurrence t^{k+1} = 2 Hhat t^k - t^{k-1},
+ * columns above from rho^{2k} = 2 t^k.t^k - rho^0 and
+ * rho^{2k-1} = 2 t^k.t^{k-1} - rho^1.  Returns SQ_EBOUNDS if a moment leaves
+ * [-1, 1] by more than rounding.  Synchronises `stream`. */
+int sq_moments(sq_ctx *ctx, double *moments, void *stream);
+
+/* Fermi level (Sec. 3.2): Brent's method on N(mu) - N_e over
+ * [min_q(chi - zeta) - 40 kT, max_q(chi + zeta) + 40 kT], with the Chebyshev
+ * coefficients taken by discrete orthogonality on n_pl + 1 Chebyshev-Gauss
+ * nodes.  moments (device) as written by sq_moments; *mu (host) receives the
+ * result.  0 < n_electrons < 2 N_d.  Synchronises `stream`. */
+int sq_fermi_level(sq_ctx *ctx, const double *moments, double n_electrons, double *mu,
+                   void *stream);
+
+/* Density and energies at Fermi level mu (Sec. 3.2-3.3): rho (device, N_d
+ * FP64) and energies (host, 4 FP64) = {E_band, E_ent, E_band + E_ent,
+ * h^3 sum_q rho_q}.  Synchronises `stream`. */
+int sq_density_energy(sq_ctx *ctx, const double *moments, double mu, double *rho,
+                      double *energies, void *stream);
+
+/* Release the host tables (never touches caller-owned device memory). */
+void sq_destroy(sq_ctx *ctx);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char *sq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SQ_H */

@@ -1,0 +1,1029 @@
+// HIP kernels of libsq for gfx950 (MI355X): spectral-quadrature density step of
+// SQDFT (arXiv 1708.07913, Sec. 3.2-3.3).
+//
+// Recurrence kernels (Lanczos bounds and Chebyshev moments) -- one workgroup
+// per region of influence at a time, persistent over nodes:
+//   * thread (x, y) owns the z-column of the cube; the current vector t^k of
+//     that column lives in VGPRs (z-neighbours of the stencil come from
+//     registers);
+//   * x/y neighbours come from a zero-padded LDS plane of t^k that is rewritten
+//     once per z (double-buffered, one barrier per plane); the zero halo is the
+//     Dirichlet truncation of Sec. 3.1;
+//   * t^{k-1} streams through a per-workgroup global slot that is read and
+//     overwritten with t^k in the same sweep (two vector passes per step);
+//   * the nonlocal projectors of every atom image in the region are applied
+//     inside the sweep through per-column z-runs built once per node; their
+//     dot products with the new vector are accumulated along each run and
+//     added into LDS at the run's end;
+//   * workgroups walk node ranges split by XCD (blockIdx % 8) so that one
+//     XCD's L2 holds neighbouring V_eff windows and projector tables.
+// FP32-mixed: vectors, LDS plane, potential window and stencil pair sums in
+// FP32; every accumulation (stencil sum, projector terms, update, dots) FP64.
+#include <hip/hip_runtime.h>
+
+#include "sq_internal.h"
+
+#include <math.h>
+
+namespace sq {
+namespace {
+
+constexpr int NO = kNoMax;
+
+template <int C>
+struct Shape {
+    static constexpr int CC = C * C;
+    static constexpr int P = C + 2 * NO;              // padded plane edge (zero halo of NO)
+    static constexpr int ROWS = P + 2 * NO + 1;       // + an all-zero neighbourhood for idle threads
+    static constexpr int PLANE = ROWS * P + 1;        // + one write-only cell for idle threads
+    static constexpr int IDLE_READ = (P + NO) * P + NO;
+    static constexpr int IDLE_WRITE = ROWS * P;
+    static constexpr int BLOCK = (CC + 63) / 64 * 64;
+    static constexpr int NW = BLOCK / 64;
+    static constexpr int MAXRUNS = 6 * CC + 512;
+};
+
+// Run record: x = image slot | z_first << 8 | z_last << 16 | chain << 24,
+// y = value base (value at plane z is pvals[y + z]).  The sentinel never
+// becomes active and never ends.
+constexpr unsigned kSentinelX = (0xFEu << 16) | (0xFFu << 8);
+constexpr unsigned kIdleOffset = 0x7FFFFF00u;  // beyond every buffer: loads read 0, stores drop
+
+template <int C, typename T>
+struct Lds {
+    T plane[2][Shape<C>::PLANE];
+    uint2 runs[Shape<C>::MAXRUNS + 1];
+    int col_start[Shape<C>::CC + 1];
+    int col_fill[Shape<C>::CC];
+    int col_na[Shape<C>::CC];
+    int img_atom[kMaxImages];
+    int img_lb[kMaxImages][3];
+    int img_prefix[kMaxImages + 1];
+    int img_run0[kMaxImages];
+    int img_nrun[kMaxImages];
+    double img_coef[kMaxImages];
+    double s[2][kMaxImages];
+    double cs[kMaxImages];
+    double red[Shape<C>::NW * 2];
+    double bc[4];
+    int scan_tot[Shape<C>::NW];
+    int ni;
+    int bad;
+    int has_b;
+};
+
+struct LanczosLds {
+    double al[kMaxLanczos];
+    double be[kMaxLanczos];
+};
+
+__device__ __forceinline__ int floor_div(int a, int b) {
+    int q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+__device__ __forceinline__ int ceil_div(int a, int b) { return -floor_div(-a, b); }
+__device__ __forceinline__ int pmod(int a, int n) {
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// Raw buffer access: SGPR descriptor + one VGPR byte offset + SGPR byte offset,
+// so that per-plane addresses stay scalar.  Out-of-range offsets read 0 and
+// drop stores (used for idle threads).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, long long bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+// Keep a running sum materialised where it is updated.  Without this the
+// compiler sinks a chain of per-plane accumulations to its single use after
+// the unrolled sweep and keeps every operand live until then.  Emits nothing.
+__device__ __forceinline__ void pin(double &x) { asm volatile("" : "+v"(x)); }
+
+// A workgroup-uniform double, moved to SGPRs (VALU ops then take it as their
+// scalar operand instead of holding a copy per lane).
+__device__ __forceinline__ double uniform(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum of (a, b) over the workgroup; the result is returned to every thread.
+template <int C, typename T>
+__device__ __forceinline__ void block_sum2(Lds<C, T> &L, double &a, double &b, int tid) {
+    constexpr int NW = Shape<C>::NW;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = tid >> 6;
+    if ((tid & 63) == 0) {
+        L.red[2 * w] = a;
+        L.red[2 * w + 1] = b;
+    }
+    __syncthreads();
+    if (tid < 2) {
+        double s = 0.0;
+        for (int i = 0; i < NW; ++i) s += L.red[2 * i + tid];
+        L.bc[tid] = s;
+    }
+    __syncthreads();
+    a = L.bc[0];
+    b = L.bc[1];
+    __syncthreads();
+}
+
+// SplitMix64 (S. Vigna): first output for a given seed, mapped to [0, 1).
+__device__ __forceinline__ double unit_from_seed(unsigned long long seed) {
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+__device__ __forceinline__ unsigned run_key(uint2 r, bool with_chain) {
+    // (chain, z_first, image slot)
+    return (with_chain ? (((r.x >> 24) & 1u) << 16) : 0u) | (((r.x >> 8) & 0xFFu) << 8) | (r.x & 0xFFu);
+}
+
+__device__ void sort_runs(uint2 *runs, int b, int e, bool with_chain) {
+    for (int i = b + 1; i < e; ++i) {
+        const uint2 r = runs[i];
+        const unsigned key = run_key(r, with_chain);
+        int j = i - 1;
+        while (j >= b && run_key(runs[j], with_chain) > key) {
+            runs[j + 1] = runs[j];
+            --j;
+        }
+        runs[j + 1] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Region of influence of node q: projector images meeting the cube and, per
+// cube column, the clipped z-runs of their spheres split into two chains of
+// non-overlapping runs (a second chain exists only where two spheres overlap).
+// ---------------------------------------------------------------------------
+template <int C, typename T>
+__device__ void setup_region(const RecurrenceArgs &A, Lds<C, T> &L, int qi, int qj, int qk, int tid) {
+    using S = Shape<C>;
+    const int n = A.n, m = A.m;
+    if (tid == 0) {
+        L.ni = 0;
+        L.bad = 0;
+        L.has_b = 0;
+        L.runs[S::MAXRUNS] = make_uint2(kSentinelX, 0u);
+    }
+    for (int i = tid; i < 2 * S::PLANE; i += S::BLOCK) (&L.plane[0][0])[i] = T(0);
+    for (int i = tid; i < S::CC; i += S::BLOCK) L.col_fill[i] = 0;
+    for (int i = tid; i < kMaxImages; i += S::BLOCK) L.s[0][i] = L.s[1][i] = 0.0;
+    __syncthreads();
+
+    // every lattice image (atom a, translation t) whose sphere's box meets the cube
+    const int lo0 = qi - m, lo1 = qj - m, lo2 = qk - m;
+    for (int a = tid; a < A.natom; a += S::BLOCK) {
+        const AtomDev at = A.atoms[a];
+        const int tl0 = ceil_div(lo0 - at.bx - at.dmax[0], n), th0 = floor_div(lo0 + C - 1 - at.bx - at.dmin[0], n);
+        const int tl1 = ceil_div(lo1 - at.by - at.dmax[1], n), th1 = floor_div(lo1 + C - 1 - at.by - at.dmin[1], n);
+        const int tl2 = ceil_div(lo2 - at.bz - at.dmax[2], n), th2 = floor_div(lo2 + C - 1 - at.bz - at.dmin[2], n);
+        for (int tz = tl2; tz <= th2; ++tz)
+            for (int ty = tl1; ty <= th1; ++ty)
+                for (int tx = tl0; tx <= th0; ++tx) {
+                    const int slot = atomicAdd(&L.ni, 1);
+                    if (slot < kMaxImages) {
+                        L.img_atom[slot] = a;
+                        L.img_lb[slot][0] = at.bx + n * tx - lo0;
+                        L.img_lb[slot][1] = at.by + n * ty - lo1;
+                        L.img_lb[slot][2] = at.bz + n * tz - lo2;
+                        L.img_coef[slot] = at.coef;
+                        L.img_run0[slot] = at.run0;
+                        L.img_nrun[slot] = at.nrun;
+                    }
+                }
+    }
+    __syncthreads();
+    int ni = L.ni;
+    if (ni > kMaxImages) {
+        if (tid == 0) atomicOr(A.flags, kFlagImages);
+        ni = kMaxImages;
+    }
+    if (tid == 0) {
+        int acc = 0;
+        for (int i = 0; i < ni; ++i) {
+            L.img_prefix[i] = acc;
+            acc += L.img_nrun[i];
+        }
+        L.img_prefix[ni] = acc;
+    }
+    __syncthreads();
+    const int npairs = L.img_prefix[ni];
+
+    // count, then place, the clipped z-runs of every image column inside the cube
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int p = tid; p < npairs; p += S::BLOCK) {
+            int lo = 0, hi = ni;  // largest I with prefix[I] <= p
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (L.img_prefix[mid] <= p) lo = mid;
+                else hi = mid;
+            }
+            const int I = lo;
+            const RunDev r = A.runs[L.img_run0[I] + (p - L.img_prefix[I])];
+            const int cx = L.img_lb[I][0] + r.dx, cy = L.img_lb[I][1] + r.dy;
+            if (cx < 0 || cx >= C || cy < 0 || cy >= C) continue;
+            const int z0 = L.img_lb[I][2] + r.dz0, z1 = z0 + r.len - 1;
+            const int zl = z0 > 0 ? z0 : 0, zh = z1 < C - 1 ? z1 : C - 1;
+            if (zl > zh) continue;
+            const int col = cy * C + cx;
+            const int pos = atomicAdd(&L.col_fill[col], 1);
+            if (pass == 1 && pos < S::MAXRUNS) {
+                L.runs[pos] = make_uint2((unsigned)I | ((unsigned)zl << 8) | ((unsigned)zh << 16),
+                                         (unsigned)(r.vstart - z0));
+            }
+        }
+        __syncthreads();
+        if (pass == 0) {
+            // exclusive scan of the per-column counts
+            int v = 0;
+            if (tid < S::CC) v = L.col_fill[tid];
+            int incl = v;
+            const int lane = tid & 63;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += t;
+            }
+            if (lane == 63) L.scan_tot[tid >> 6] = incl;
+            __syncthreads();
+            int base = 0;
+            for (int w = 0; w < (tid >> 6); ++w) base += L.scan_tot[w];
+            if (tid < S::CC) {
+                L.col_start[tid] = base + incl - v;
+                L.col_fill[tid] = base + incl - v;
+                if (tid == S::CC - 1) {
+                    L.col_start[S::CC] = base + incl;
+                    if (base + incl > S::MAXRUNS) L.bad = 1;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (L.bad) {
+        if (tid == 0) atomicOr(A.flags, kFlagRuns);
+        if (tid <= S::CC) L.col_start[tid] = 0;
+        __syncthreads();
+    }
+    // per column: sort by z_first, split into two chains of disjoint runs,
+    // and order chain 0 before chain 1
+    if (tid < S::CC) {
+        const int b = L.col_start[tid], e = L.col_start[tid + 1];
+        sort_runs(L.runs, b, e, false);
+        int last0 = -1, last1 = -1, na = 0;
+        bool two = false;
+        for (int i = b; i < e; ++i) {
+            uint2 r = L.runs[i];
+            const int zf = (int)((r.x >> 8) & 0xFFu), zl = (int)((r.x >> 16) & 0xFFu);
+            if (zf > last0) {
+                last0 = zl;
+                ++na;
+            } else if (zf > last1) {
+                last1 = zl;
+                r.x |= 1u << 24;
+                two = true;
+            } else {
+                atomicOr(A.flags, kFlagOverlap);
+            }
+            L.runs[i] = r;
+        }
+        if (two) {
+            sort_runs(L.runs, b, e, true);
+            L.has_b = 1;
+        }
+        L.col_na[tid] = na;
+    }
+    __syncthreads();
+}
+
+// One chain of disjoint z-runs of a column, walked plane by plane without
+// branches except at the end of a run.
+struct Chain {
+    int i, e;
+    int z0, z1, vb, sl;
+    double acc;
+
+    __device__ __forceinline__ void load(const uint2 *runs, int sentinel) {
+        const uint2 r = runs[i < e ? i : sentinel];
+        sl = (int)(r.x & 0xFFu);
+        z0 = (int)((r.x >> 8) & 0xFFu);
+        z1 = (int)((r.x >> 16) & 0xFFu);
+        vb = (int)r.y;
+    }
+    __device__ __forceinline__ void start(const uint2 *runs, int b, int end, int sentinel) {
+        i = b;
+        e = end;
+        acc = 0.0;
+        load(runs, sentinel);
+    }
+    // projector value at plane z (0 outside the current run)
+    __device__ __forceinline__ double value(__amdgpu_buffer_rsrc_t pv, int z) const {
+        const bool act = (z >= z0) & (z <= z1);
+        return bload<double>(pv, act ? (unsigned)(vb + z) * 8u : kIdleOffset, 0u);
+    }
+    // after plane z: a finished run adds its dot product into s[slot]
+    __device__ __forceinline__ void finish(double *s, int z, const uint2 *runs, int sentinel) {
+        if (z == z1) {
+            atomicAdd(&s[sl], acc);
+            acc = 0.0;
+            ++i;
+            load(runs, sentinel);
+        }
+    }
+};
+
+template <int C, typename T>
+__device__ __forceinline__ void chains_start(const Lds<C, T> &L, int tid, bool active, Chain &ca, Chain &cb) {
+    constexpr int SENT = Shape<C>::MAXRUNS;
+    const int b = active ? L.col_start[tid] : 0;
+    const int e = active ? L.col_start[tid + 1] : 0;
+    const int na = active ? L.col_na[tid] : 0;
+    ca.start(L.runs, b, b + na, SENT);
+    cb.start(L.runs, b + na, e, SENT);
+}
+
+__device__ __forceinline__ void node_coords(long long q, int n, int &qi, int &qj, int &qk) {
+    qi = (int)(q % n);
+    qj = (int)((q / n) % n);
+    qk = (int)(q / ((long long)n * n));
+}
+
+// Projector dots of the register column tv: s[dst][I] += p_I . tv
+template <int C, typename T, typename V>
+__device__ __forceinline__ void projector_dots(Lds<C, T> &L, __amdgpu_buffer_rsrc_t pvr, const V (&tv)[C],
+                                               int dst, int tid, bool active, bool has_b) {
+    constexpr int SENT = Shape<C>::MAXRUNS;
+    Chain ca, cb;
+    chains_start(L, tid, active, ca, cb);
+#pragma unroll
+    for (int z = 0; z < C; ++z) {
+        const double t = (double)tv[z];
+        ca.acc += ca.value(pvr, z) * t;
+        pin(ca.acc);
+        ca.finish(L.s[dst], z, L.runs, SENT);
+        if (has_b) {
+            cb.acc += cb.value(pvr, z) * t;
+            pin(cb.acc);
+            cb.finish(L.s[dst], z, L.runs, SENT);
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev recurrence and moments (Sec. 3.2):
+//   t^0 = e_q, t^1 = Hhat t^0, t^{k+1} = 2 Hhat t^k - t^{k-1},
+//   rho^j = t^j[q] (j <= n_pl/2), rho^{2k} = 2 t^k.t^k - rho^0,
+//   rho^{2k-1} = 2 t^k.t^{k-1} - rho^1 (k > n_pl/4).
+// ---------------------------------------------------------------------------
+template <int C, typename T>
+__global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs A) {
+    using S = Shape<C>;
+    constexpr int MC = (C - 1) / 2;
+    constexpr int SENT = S::MAXRUNS;
+    __shared__ Lds<C, T> L;
+    const int tid = threadIdx.x;
+    const bool active = tid < S::CC;
+    const int x = active ? tid % C : 0, y = active ? tid / C : 0;
+    // neighbourhood corner: every stencil read is corner + a positive immediate
+    const int pcr = active ? (y + NO) * S::P + (x + NO) : S::IDLE_READ;
+    const int corner = pcr - NO * S::P - NO;
+    const int pcw = active ? pcr : S::IDLE_WRITE;
+    const bool is_centre = (tid == MC * C + MC);
+    const int n = A.n;
+    const int npl = A.npl, half = npl / 2;
+    const __amdgpu_buffer_rsrc_t slr =
+        make_rsrc(reinterpret_cast<T *>(A.slots) + (long long)blockIdx.x * A.slot_elems, A.slot_elems * (long long)sizeof(T));
+    const __amdgpu_buffer_rsrc_t vr = sizeof(T) == 4 ? make_rsrc(A.veff32, A.nd * 4) : make_rsrc(A.veff, A.nd * 8);
+    const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
+    const unsigned voff = active ? (unsigned)tid * (unsigned)sizeof(T) : kIdleOffset;
+    const int nwg = gridDim.x, xcd = blockIdx.x & 7, per = nwg >> 3, lw = blockIdx.x >> 3;
+    const long long qlo = A.nd * xcd / 8, qhi = A.nd * (xcd + 1) / 8;
+    const double kin0 = -3.0 * A.w[0];
+
+    for (long long q = qlo + lw; q < qhi; q += per) {
+        int qi, qj, qk;
+        node_coords(q, n, qi, qj, qk);
+        setup_region(A, L, qi, qj, qk, tid);
+        const int ni = L.ni < kMaxImages ? L.ni : kMaxImages;
+        const bool has_b = L.has_b != 0;
+        const unsigned zbase = (unsigned)pmod(qk - A.m, n);
+        const double chi = uniform(A.chi[q]), zeta = uniform(A.zeta[q]);
+        const double invz = uniform(1.0 / zeta);
+        double kw[NO + 1];
+#pragma unroll
+        for (int d = 1; d <= NO; ++d) kw[d] = uniform(-0.5 * A.w[d] * invz);
+        const double c0 = uniform(kin0 - chi);
+        const unsigned vcol =
+            active ? (unsigned)(pmod(qi - A.m + x, n) + n * pmod(qj - A.m + y, n)) * (unsigned)sizeof(T) : kIdleOffset;
+        double *mrow = A.moments + q * (long long)(npl + 1);
+
+        T tv[C];
+#pragma unroll
+        for (int z = 0; z < C; ++z) tv[z] = T((is_centre && z == MC) ? 1 : 0);
+        if (tid == 0) mrow[0] = 1.0;
+        int cur = 0;
+        projector_dots(L, pvr, tv, cur, tid, active, has_b);
+
+        for (int k = 0; k < half; ++k) {
+            const double al = k == 0 ? 1.0 : 2.0;
+            const double scale = uniform(al * invz);
+            for (int i = tid; i < kMaxImages; i += S::BLOCK)
+                L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur][i] : 0.0;
+            Chain ca, cb;
+            chains_start(L, tid, active, ca, cb);
+            double *snext = L.s[cur ^ 1];
+            double d1 = 0.0, d2 = 0.0;
+            unsigned zb = zbase;
+            asm volatile("" : "+s"(zb));  // keep the per-plane offsets inside the step loop
+            T nv[C];
+#pragma unroll
+            for (int z = 0; z < C; ++z) {
+                const unsigned sz = (unsigned)(z * S::CC) * (unsigned)sizeof(T);
+                const unsigned vz_off = (unsigned)(n * n) * ((zb + (unsigned)z) % (unsigned)n) * (unsigned)sizeof(T);
+                const double vz = (double)bload<T>(vr, vcol, vz_off);
+                double tprev = 0.0;
+                if (k > 0) tprev = (double)bload<T>(slr, voff, sz);
+                L.plane[z & 1][pcw] = tv[z];
+                __syncthreads();
+                const T *pl = L.plane[z & 1] + corner;
+                constexpr int PC = NO * S::P + NO;
+                double acc = 0.0;
+#pragma unroll
+                for (int d = 1; d <= NO; ++d) {
+                    const T xs = pl[PC + d] + pl[PC - d];
+                    const T ys = pl[PC + d * S::P] + pl[PC - d * S::P];
+                    T zs = T(0);
+                    if (z + d < C) zs = tv[z + d];
+                    if (z - d >= 0) zs = zs + tv[z - d];
+                    acc += kw[d] * ((double)xs + (double)ys + (double)zs);
+                }
+                const double tz = (double)tv[z];
+                const double u = acc + (vz + c0) * invz * tz;
+                const double pa = ca.value(pvr, z);
+                double nvd = al * u + L.cs[ca.sl] * pa - tprev;
+                double pb = 0.0;
+                if (has_b) {
+                    pb = cb.value(pvr, z);
+                    nvd += L.cs[cb.sl] * pb;
+                }
+                const T nvt = T(nvd);
+                nvd = (double)nvt;
+                nv[z] = nvt;
+                bstore(tv[z], slr, voff, sz);
+                d1 += nvd * nvd;
+                d2 += nvd * tz;
+                pin(d1);
+                pin(d2);
+                ca.acc += pa * nvd;
+                pin(ca.acc);
+                ca.finish(snext, z, L.runs, SENT);
+                if (has_b) {
+                    cb.acc += pb * nvd;
+                    pin(cb.acc);
+                    cb.finish(snext, z, L.runs, SENT);
+                }
+                if (z == MC && is_centre) {
+                    mrow[k + 1] = nvd;
+                    if (k == 0) L.bc[2] = nvd;
+                    if (fabs(nvd) > 1.0 + A.bounds_tol) atomicOr(A.flags, kFlagBounds);
+                }
+            }
+            __syncthreads();
+            // reduce every step: a conditional reduction lets the compiler sink
+            // the per-plane products into it and keep them all live
+            block_sum2(L, d1, d2, tid);
+            if (k + 1 > half / 2) {
+                if (tid == 0) {
+                    const double r2k = 2.0 * d1 - 1.0, r2k1 = 2.0 * d2 - L.bc[2];
+                    mrow[2 * (k + 1)] = r2k;
+                    mrow[2 * (k + 1) - 1] = r2k1;
+                    if (fabs(r2k) > 1.0 + A.bounds_tol || fabs(r2k1) > 1.0 + A.bounds_tol)
+                        atomicOr(A.flags, kFlagBounds);
+                }
+            }
+#pragma unroll
+            for (int z = 0; z < C; ++z) tv[z] = nv[z];
+            for (int i = tid; i < kMaxImages; i += S::BLOCK) L.s[cur][i] = 0.0;
+            cur ^= 1;
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos spectral bounds (Sec. 3.2): Paige's ordering of the three-term
+// recurrence from a fixed SplitMix64 start vector, no reorthogonalisation,
+// extreme eigenvalues of the tridiagonal by Sturm bisection.
+// ---------------------------------------------------------------------------
+__device__ int sturm_count(int k, const double *a, const double *b, double x, double pivmin) {
+    int cnt = 0;
+    double d = a[0] - x;
+    if (fabs(d) < pivmin) d = -pivmin;
+    if (d < 0) ++cnt;
+    for (int i = 1; i < k; ++i) {
+        d = (a[i] - x) - b[i - 1] * b[i - 1] / d;
+        if (fabs(d) < pivmin) d = -pivmin;
+        if (d < 0) ++cnt;
+    }
+    return cnt;
+}
+
+__device__ double sturm_bisect(int k, const double *a, const double *b, int target) {
+    double lo = INFINITY, hi = -INFINITY, bmax2 = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < k - 1 ? fabs(b[i]) : 0.0);
+        lo = fmin(lo, a[i] - r);
+        hi = fmax(hi, a[i] + r);
+        if (i < k - 1) bmax2 = fmax(bmax2, b[i] * b[i]);
+    }
+    const double pivmin = 2.2250738585072014e-308 * fmax(bmax2, 1.0);
+    for (int it = 0; it < 256; ++it) {
+        const double mid = lo + 0.5 * (hi - lo);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(k, a, b, mid, pivmin) >= target) hi = mid;
+        else lo = mid;
+    }
+    return hi;
+}
+
+template <int C>
+__global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs A) {
+    using S = Shape<C>;
+    using T = double;
+    constexpr int SENT = S::MAXRUNS;
+    __shared__ Lds<C, T> L;
+    __shared__ LanczosLds LL;
+    const int tid = threadIdx.x;
+    const bool active = tid < S::CC;
+    const int x = active ? tid % C : 0, y = active ? tid / C : 0;
+    const int pcr = active ? (y + NO) * S::P + (x + NO) : S::IDLE_READ;
+    const int corner = pcr - NO * S::P - NO;
+    const int pcw = active ? pcr : S::IDLE_WRITE;
+    const int n = A.n;
+    const __amdgpu_buffer_rsrc_t slr =
+        make_rsrc(reinterpret_cast<T *>(A.slots) + (long long)blockIdx.x * A.slot_elems, A.slot_elems * 8);
+    const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
+    const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
+    const unsigned voff = active ? (unsigned)tid * 8u : kIdleOffset;
+    const int nwg = gridDim.x, xcd = blockIdx.x & 7, per = nwg >> 3, lw = blockIdx.x >> 3;
+    const long long qlo = A.nd * xcd / 8, qhi = A.nd * (xcd + 1) / 8;
+    const double kin0 = -3.0 * A.w[0];
+    double kw[NO + 1];
+#pragma unroll
+    for (int d = 1; d <= NO; ++d) kw[d] = -0.5 * A.w[d];
+    const long long ns = (long long)C * C * C;
+    const int kmax = (long long)A.n_lanczos < ns ? A.n_lanczos : (int)ns;
+
+    for (long long q = qlo + lw; q < qhi; q += per) {
+        int qi, qj, qk;
+        node_coords(q, n, qi, qj, qk);
+        setup_region(A, L, qi, qj, qk, tid);
+        const int ni = L.ni < kMaxImages ? L.ni : kMaxImages;
+        const bool has_b = L.has_b != 0;
+        const unsigned zbase = (unsigned)pmod(qk - A.m, n);
+        const unsigned vcol = active ? (unsigned)(pmod(qi - A.m + x, n) + n * pmod(qj - A.m + y, n)) * 8u : kIdleOffset;
+
+        double tv[C];
+#pragma unroll
+        for (int z = 0; z < C; ++z)
+            tv[z] = active ? (unit_from_seed((unsigned long long)(x + C * (y + C * z))) - 0.5) / A.start_norm : 0.0;
+        int cur = 0;
+        projector_dots(L, pvr, tv, cur, tid, active, has_b);
+
+        double bprev = 0.0, gersh = 0.0;
+        int ksteps = kmax;
+        for (int j = 0; j < kmax; ++j) {
+            // w = H v - beta_{j-1} v_{j-1};  slot <- v;  alpha = w . v
+            for (int i = tid; i < kMaxImages; i += S::BLOCK)
+                L.cs[i] = i < ni ? L.img_coef[i] * L.s[cur][i] : 0.0;
+            Chain ca, cb;
+            chains_start(L, tid, active, ca, cb);
+            unsigned zb = zbase;
+            asm volatile("" : "+s"(zb));
+            double wv[C];
+            double da = 0.0;
+#pragma unroll
+            for (int z = 0; z < C; ++z) {
+                const unsigned sz = (unsigned)(z * S::CC) * 8u;
+                const unsigned vz_off = (unsigned)(n * n) * ((zb + (unsigned)z) % (unsigned)n) * 8u;
+                const double vz = bload<double>(vr, vcol, vz_off);
+                double vprev = 0.0;
+                if (j > 0) vprev = bload<double>(slr, voff, sz);
+                L.plane[z & 1][pcw] = tv[z];
+                __syncthreads();
+                const double *pl = L.plane[z & 1] + corner;
+                constexpr int PC = NO * S::P + NO;
+                double acc = 0.0;
+#pragma unroll
+                for (int d = 1; d <= NO; ++d) {
+                    const double xs = pl[PC + d] + pl[PC - d];
+                    const double ys = pl[PC + d * S::P] + pl[PC - d * S::P];
+                    double zs = 0.0;
+                    if (z + d < C) zs = tv[z + d];
+                    if (z - d >= 0) zs = zs + tv[z - d];
+                    acc += kw[d] * (xs + ys + zs);
+                }
+                double u = acc + (vz + kin0) * tv[z];
+                u += L.cs[ca.sl] * ca.value(pvr, z);
+                if (has_b) u += L.cs[cb.sl] * cb.value(pvr, z);
+                ca.finish(L.s[cur ^ 1], z, L.runs, SENT);   // advance only; accumulators stay 0
+                if (has_b) cb.finish(L.s[cur ^ 1], z, L.runs, SENT);
+                u -= bprev * vprev;
+                bstore(tv[z], slr, voff, sz);
+                wv[z] = u;
+                da += u * tv[z];
+                pin(da);
+            }
+            __syncthreads();
+            double dummy = 0.0;
+            block_sum2(L, da, dummy, tid);
+            const double alpha = uniform(da);
+
+            // w -= alpha v;  beta = |w|;  projector dots of w
+            chains_start(L, tid, active, ca, cb);
+            double db = 0.0;
+#pragma unroll
+            for (int z = 0; z < C; ++z) {
+                const double v = bload<double>(slr, voff, (unsigned)(z * S::CC) * 8u);
+                const double w = wv[z] - alpha * v;
+                wv[z] = w;
+                db += w * w;
+                pin(db);
+                ca.acc += ca.value(pvr, z) * w;
+                pin(ca.acc);
+                ca.finish(L.s[cur ^ 1], z, L.runs, SENT);
+                if (has_b) {
+                    cb.acc += cb.value(pvr, z) * w;
+                    pin(cb.acc);
+                    cb.finish(L.s[cur ^ 1], z, L.runs, SENT);
+                }
+            }
+            __syncthreads();
+            block_sum2(L, db, dummy, tid);
+            const double beta = uniform(sqrt(db));
+            if (tid == 0) {
+                LL.al[j] = alpha;
+                LL.be[j] = beta;
+                if (!isfinite(alpha) || !isfinite(beta)) atomicOr(A.flags, kFlagLanczos);
+            }
+            gersh = fmax(gersh, fabs(alpha) + beta + bprev);
+            if (j == kmax - 1 || beta <= 1e-13 * gersh) {
+                ksteps = j + 1;
+                break;
+            }
+#pragma unroll
+            for (int z = 0; z < C; ++z) tv[z] = wv[z] / beta;
+            for (int i = tid; i < kMaxImages; i += S::BLOCK) {
+                L.s[cur ^ 1][i] = L.s[cur ^ 1][i] / beta;
+                L.s[cur][i] = 0.0;
+            }
+            cur ^= 1;
+            bprev = beta;
+            __syncthreads();
+        }
+        __syncthreads();
+        if (tid < 2) L.bc[tid] = sturm_bisect(ksteps, LL.al, LL.be, tid == 0 ? 1 : ksteps);
+        __syncthreads();
+        if (tid == 0) {
+            const double lmn = L.bc[0], lmx = L.bc[1];
+            if (A.lmin) A.lmin[q] = lmn;
+            if (A.lmax) A.lmax[q] = lmx;
+            A.chi[q] = 0.5 * (lmx + lmn);
+            A.zeta[q] = (1.0 + A.margin) * 0.5 * (lmx - lmn);
+        }
+        __syncthreads();
+    }
+}
+
+#if defined(SQ_COMMON_ONLY) || !defined(SQ_CUBES)
+// ---------------------------------------------------------------------------
+// Fermi level, density and energies (Sec. 3.2-3.3).  The Chebyshev sums are
+// regrouped through per-node quadrature weights
+//   W_qk = sum_j c-table[j][k] rho_q^j,  c-table[j][k] = (2 - delta_j0)/N_q cos(j theta_k),
+// so that sum_j c_q^j rho_q^j = sum_k g(lambda_qk) W_qk with
+// lambda_qk = zeta_q r_k + chi_q (same quadrature, regrouped).
+// ---------------------------------------------------------------------------
+__global__ void set_bounds_kernel(const double *lmin, const double *lmax, double *chi, double *zeta,
+                                  long long nd, double margin) {
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nd;
+         q += (long long)gridDim.x * blockDim.x) {
+        chi[q] = 0.5 * (lmax[q] + lmin[q]);
+        zeta[q] = (1.0 + margin) * 0.5 * (lmax[q] - lmin[q]);
+    }
+}
+
+__global__ void to_fp32_kernel(const double *src, float *dst, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+__global__ void weights_kernel(const double *mom, const double *ctab, double *W, long long nd, int npl) {
+    const int nq = npl + 1;
+    const long long total = nd * nq;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long q = i / nq;
+        const int k = (int)(i - q * nq);
+        const double *r = mom + q * nq;
+        double s = 0.0;
+        for (int j = 0; j < nq; ++j) s += ctab[j * nq + k] * r[j];
+        W[i] = s;
+    }
+}
+
+__device__ __forceinline__ double fermi_fn(double x) { return 1.0 / (1.0 + exp(x)); }
+
+__device__ __forceinline__ double entropy_fn(double x) {
+    const double ax = fabs(x), e = exp(-ax);
+    return -(log1p(e) + ax * e / (1.0 + e));
+}
+
+constexpr int kRedBlock = 256;
+
+__device__ __forceinline__ double block_reduce(double v, double *sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kRedBlock / 64; ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+__global__ __launch_bounds__(kRedBlock) void extent_kernel(const double *chi, const double *zeta,
+                                                           long long nd, double *partials) {
+    __shared__ double sh[kRedBlock / 64];
+    double lo = INFINITY, hi = -INFINITY;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nd;
+         q += (long long)gridDim.x * blockDim.x) {
+        lo = fmin(lo, chi[q] - zeta[q]);
+        hi = fmax(hi, chi[q] + zeta[q]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    __shared__ double sh2[kRedBlock / 64];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = lo;
+        sh2[w] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kRedBlock / 64; ++i) {
+            lo = fmin(lo, sh[i]);
+            hi = fmax(hi, sh2[i]);
+        }
+        partials[2 * blockIdx.x] = lo;
+        partials[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+__global__ void extent_final(const double *partials, int nblk, double *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int i = 0; i < nblk; ++i) {
+            lo = fmin(lo, partials[2 * i]);
+            hi = fmax(hi, partials[2 * i + 1]);
+        }
+        out[0] = lo;
+        out[1] = hi;
+    }
+}
+
+__global__ __launch_bounds__(kRedBlock) void count_kernel(const double *W, const double *chi,
+                                                          const double *zeta, const double *rk,
+                                                          long long nd, int nq, double mu, double kT,
+                                                          double *partials) {
+    __shared__ double sh[kRedBlock / 64];
+    const long long total = nd * nq;
+    double acc = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long q = i / nq;
+        const int k = (int)(i - q * nq);
+        const double lam = zeta[q] * rk[k] + chi[q];
+        acc += fermi_fn((lam - mu) / kT) * W[i];
+    }
+    const double s = block_reduce(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kRedBlock) void density_kernel(const double *W, const double *chi,
+                                                            const double *zeta, const double *rk,
+                                                            long long nd, int nq, double mu, double kT,
+                                                            double h3, double *rho, double *partials) {
+    __shared__ double sh[kRedBlock / 64];
+    double eb = 0.0, en = 0.0, er = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nd;
+         q += (long long)gridDim.x * blockDim.x) {
+        const double c = chi[q], z = zeta[q];
+        const double *w = W + q * nq;
+        double sg = 0.0, sb = 0.0, se = 0.0;
+        for (int k = 0; k < nq; ++k) {
+            const double lam = z * rk[k] + c;
+            const double x = (lam - mu) / kT;
+            const double g = fermi_fn(x);
+            sg += g * w[k];
+            sb += lam * g * w[k];
+            se += entropy_fn(x) * w[k];
+        }
+        const double r = 2.0 / h3 * sg;
+        rho[q] = r;
+        eb += 2.0 * sb;
+        en += 2.0 * kT * se;
+        er += r;
+    }
+    const double a = block_reduce(eb, sh);
+    const double b = block_reduce(en, sh);
+    const double c = block_reduce(er, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = a;
+        partials[3 * blockIdx.x + 1] = b;
+        partials[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// Fixed-order sum of `width` interleaved partial arrays (deterministic).
+__global__ void sum_partials(const double *partials, int nblk, int width, double *out) {
+    const int j = threadIdx.x;
+    if (blockIdx.x == 0 && j < width) {
+        double s = 0.0;
+        for (int i = 0; i < nblk; ++i) s += partials[width * i + j];
+        out[j] = s;
+    }
+}
+
+#endif  // common part
+
+}  // namespace
+
+#define SQ_ALL_CUBES X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29) X(31)
+
+#ifndef SQ_COMMON_ONLY
+// Per-cube entry points of this translation unit (SQ_CUBES lists its cubes).
+#define X(c)                                                                                        \
+    hipError_t lanczos_c##c(const RecurrenceArgs &a, int nwg, hipStream_t s) {                      \
+        hipLaunchKernelGGL(lanczos_kernel<c>, dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);           \
+        return hipGetLastError();                                                                   \
+    }                                                                                               \
+    hipError_t moments_c##c(const RecurrenceArgs &a, bool mixed, int nwg, hipStream_t s) {          \
+        if (mixed)                                                                                  \
+            hipLaunchKernelGGL((moments_kernel<c, float>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
+        else                                                                                        \
+            hipLaunchKernelGGL((moments_kernel<c, double>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
+        return hipGetLastError();                                                                   \
+    }                                                                                               \
+    hipError_t occupancy_c##c(bool lanczos, bool mixed, int *nb) {                                  \
+        if (lanczos)                                                                                \
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c>, Shape<c>::BLOCK, 0); \
+        if (mixed)                                                                                  \
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float>, Shape<c>::BLOCK, 0); \
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double>, Shape<c>::BLOCK, 0); \
+    }                                                                                               \
+    int block_c##c() { return Shape<c>::BLOCK; }
+#ifdef SQ_CUBES
+SQ_CUBES
+#else
+SQ_ALL_CUBES
+#endif
+#undef X
+#endif  // !SQ_COMMON_ONLY
+
+#if defined(SQ_COMMON_ONLY) || !defined(SQ_CUBES)
+#define X(c)                                                                         \
+    hipError_t lanczos_c##c(const RecurrenceArgs &a, int nwg, hipStream_t s);       \
+    hipError_t moments_c##c(const RecurrenceArgs &a, bool mixed, int nwg, hipStream_t s); \
+    hipError_t occupancy_c##c(bool lanczos, bool mixed, int *nb);                   \
+    int block_c##c();
+SQ_ALL_CUBES
+#undef X
+
+int recurrence_block(int C) {
+    switch (C) {
+#define X(c) case c: return block_c##c();
+        SQ_ALL_CUBES
+#undef X
+        default: return 0;
+    }
+}
+
+hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int *blocks_per_cu) {
+    switch (C) {
+#define X(c) case c: return occupancy_c##c(lanczos, mixed, blocks_per_cu);
+        SQ_ALL_CUBES
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_lanczos(const RecurrenceArgs &a, int nwg, hipStream_t s) {
+    switch (a.C) {
+#define X(c) case c: return lanczos_c##c(a, nwg, s);
+        SQ_ALL_CUBES
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_moments(const RecurrenceArgs &a, bool mixed, int nwg, hipStream_t s) {
+    switch (a.C) {
+#define X(c) case c: return moments_c##c(a, mixed, nwg, s);
+        SQ_ALL_CUBES
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+static int grid_for(long long work, int block) {
+    long long g = (work + block - 1) / block;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_set_bounds(const double *lmin, const double *lmax, double *chi, double *zeta,
+                             long long nd, double margin, hipStream_t s) {
+    hipLaunchKernelGGL(set_bounds_kernel, dim3(grid_for(nd, 256)), dim3(256), 0, s, lmin, lmax, chi, zeta,
+                       nd, margin);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_fp32(const double *src, float *dst, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(to_fp32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_quadrature_weights(const double *mom, const double *ctab, double *W, long long nd,
+                                     int npl, hipStream_t s) {
+    hipLaunchKernelGGL(weights_kernel, dim3(grid_for(nd * (npl + 1), 256)), dim3(256), 0, s, mom, ctab, W,
+                       nd, npl);
+    return hipGetLastError();
+}
+
+hipError_t launch_extent(const double *chi, const double *zeta, long long nd, double *partials, int nblk,
+                         double *out, hipStream_t s) {
+    hipLaunchKernelGGL(extent_kernel, dim3(nblk), dim3(kRedBlock), 0, s, chi, zeta, nd, partials);
+    hipLaunchKernelGGL(extent_final, dim3(1), dim3(64), 0, s, partials, nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const double *W, const double *chi, const double *zeta, const double *rk,
+                        long long nd, int nq, double mu, double kT, double *partials, int nblk, double *out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(count_kernel, dim3(nblk), dim3(kRedBlock), 0, s, W, chi, zeta, rk, nd, nq, mu, kT,
+                       partials);
+    hipLaunchKernelGGL(sum_partials, dim3(1), dim3(64), 0, s, partials, nblk, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_density(const double *W, const double *chi, const double *zeta, const double *rk,
+                          long long nd, int nq, double mu, double kT, double h3, double *rho,
+                          double *partials, int nblk, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(density_kernel, dim3(nblk), dim3(kRedBlock), 0, s, W, chi, zeta, rk, nd, nq, mu, kT,
+                       h3, rho, partials);
+    hipLaunchKernelGGL(sum_partials, dim3(1), dim3(64), 0, s, partials, nblk, 3, out);
+    return hipGetLastError();
+}
+
+#endif
+
+}  // namespace sq

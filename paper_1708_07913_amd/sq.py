@@ -1,0 +1,203 @@
+"""Thin Python binding of libsq (include/sq.h): argument marshalling only.
+
+PyTorch provides the device memory (workspace, V_eff, bounds, moments,
+density) and the stream; every step of the SQ density/energy path runs in the
+HIP kernels of libsq.so.  Loading fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsq.so")
+
+FP64 = 0
+FP32_MIXED = 1
+
+SQ_OK = 0
+_STATUS = {-1: "SQ_EINVAL", -2: "SQ_ENOMEM", -3: "SQ_EDEVICE", -4: "SQ_ESTATE", -5: "SQ_ENOCONV",
+           -6: "SQ_EBOUNDS", -7: "SQ_ECAPACITY"}
+
+
+class SQError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {message}")
+        self.code = code
+
+
+class Options(ct.Structure):
+    _fields_ = [("precision", ct.c_int), ("n_lanczos", ct.c_int), ("margin", ct.c_double),
+                ("mu_xtol", ct.c_double), ("ne_rtol", ct.c_double), ("max_brent", ct.c_int),
+                ("workgroups", ct.c_int)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libsq.so from the package directory (never a CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ct.CDLL(LIB_PATH)
+    P, D, I, S = ct.c_void_p, ct.c_double, ct.c_int, ct.c_size_t
+    dp = ct.POINTER(ct.c_double)
+    lib.sq_default_options.argtypes = [ct.POINTER(Options)]
+    lib.sq_default_options.restype = None
+    lib.sq_last_error.restype = ct.c_char_p
+    lib.sq_setup.argtypes = [ct.POINTER(P), D, D, I, D, I, D, I, dp, dp, ct.POINTER(Options)]
+    lib.sq_query.argtypes = [P, ct.POINTER(I), ct.POINTER(I), ct.POINTER(ct.c_longlong), ct.POINTER(S)]
+    lib.sq_bind.argtypes = [P, P, S, P, P]
+    lib.sq_update_veff.argtypes = [P, P, P]
+    lib.sq_spectral_bounds.argtypes = [P, P, P, P]
+    lib.sq_set_bounds.argtypes = [P, P, P, P]
+    lib.sq_moments.argtypes = [P, P, P]
+    lib.sq_fermi_level.argtypes = [P, P, D, dp, P]
+    lib.sq_density_energy.argtypes = [P, P, D, P, dp, P]
+    lib.sq_destroy.argtypes = [P]
+    lib.sq_destroy.restype = None
+    for name in ("sq_setup", "sq_query", "sq_bind", "sq_update_veff", "sq_spectral_bounds",
+                 "sq_set_bounds", "sq_moments", "sq_fermi_level", "sq_density_energy"):
+        getattr(lib, name).restype = ct.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != SQ_OK:
+        raise SQError(code, _lib.sq_last_error().decode())
+
+
+def default_options() -> Options:
+    o = Options()
+    load_library().sq_default_options(ct.byref(o))
+    return o
+
+
+def _dptr(t) -> int:
+    return t.data_ptr()
+
+
+class SQ:
+    """One snapshot on the current CUDA (HIP) device.
+
+    veff: torch float64 tensor of n^3 values on the device (kept alive here).
+    """
+
+    def __init__(self, cell, h, fd_order, rcut, npl, kT, atoms, kb, veff, precision=FP64,
+                 n_lanczos=50, margin=0.05, workgroups=0, stream=None):
+        import torch
+        lib = load_library()
+        self.torch = torch
+        opt = default_options()
+        opt.precision = int(precision)
+        opt.n_lanczos = int(n_lanczos)
+        opt.margin = float(margin)
+        opt.workgroups = int(workgroups)
+        atoms = np.ascontiguousarray(np.asarray(atoms, dtype=np.float64).reshape(-1, 3))
+        kb = np.ascontiguousarray(np.asarray(kb, dtype=np.float64).reshape(-1, 3))
+        natom = atoms.shape[0]
+        ctx = ct.c_void_p()
+        dp = ct.POINTER(ct.c_double)
+        _check(lib.sq_setup(ct.byref(ctx), float(cell), float(h), int(fd_order), float(rcut), int(npl),
+                            float(kT), natom, atoms.ctypes.data_as(dp) if natom else None,
+                            kb.ctypes.data_as(dp) if natom else None, ct.byref(opt)))
+        self._ctx = ctx
+        n, m, nd, ws = ct.c_int(), ct.c_int(), ct.c_longlong(), ct.c_size_t()
+        _check(lib.sq_query(ctx, ct.byref(n), ct.byref(m), ct.byref(nd), ct.byref(ws)))
+        self.n, self.m, self.nd, self.workspace_bytes = n.value, m.value, nd.value, ws.value
+        self.npl = int(npl)
+        self.kT = float(kT)
+        self.precision = int(precision)
+        self.h = float(cell) / self.n
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._stream = stream
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.veff = self._as_veff(veff)
+        _check(lib.sq_bind(ctx, self._ws_ptr, self.workspace_bytes, _dptr(self.veff), self._stream_ptr()))
+
+    @classmethod
+    def from_workload(cls, wl, veff=None, precision=None, **kw):
+        import torch
+        if veff is None:
+            veff = torch.from_numpy(wl.veff()).to("cuda")
+        if precision is None:
+            precision = FP32_MIXED if wl.precision == "mixed" else FP64
+        return cls(wl.cell, wl.h, wl.fd_order, wl.rcut, wl.npl, wl.kT, wl.atoms, wl.kb, veff,
+                   precision=precision, **kw)
+
+    def _as_veff(self, veff):
+        torch = self.torch
+        if not isinstance(veff, torch.Tensor):
+            veff = torch.from_numpy(np.ascontiguousarray(veff, dtype=np.float64))
+        veff = veff.to(device=self.device, dtype=torch.float64).contiguous()
+        if veff.numel() != self.nd:
+            raise ValueError(f"veff must have {self.nd} entries")
+        return veff
+
+    def _stream_ptr(self):
+        s = self._stream if self._stream is not None else self.torch.cuda.current_stream(self.device)
+        return s.cuda_stream
+
+    def __del__(self):
+        if getattr(self, "_ctx", None) and _lib is not None:
+            _lib.sq_destroy(self._ctx)
+            self._ctx = None
+
+    # -- the five steps -------------------------------------------------------------
+    def update_veff(self, veff):
+        self.veff = self._as_veff(veff)
+        _check(_lib.sq_update_veff(self._ctx, _dptr(self.veff), self._stream_ptr()))
+
+    def spectral_bounds(self):
+        torch = self.torch
+        lmin = torch.empty(self.nd, dtype=torch.float64, device=self.device)
+        lmax = torch.empty(self.nd, dtype=torch.float64, device=self.device)
+        _check(_lib.sq_spectral_bounds(self._ctx, _dptr(lmin), _dptr(lmax), self._stream_ptr()))
+        return lmin, lmax
+
+    def set_bounds(self, lmin, lmax):
+        torch = self.torch
+        self._lmin = torch.as_tensor(lmin, dtype=torch.float64).to(self.device).contiguous()
+        self._lmax = torch.as_tensor(lmax, dtype=torch.float64).to(self.device).contiguous()
+        if self._lmin.numel() != self.nd or self._lmax.numel() != self.nd:
+            raise ValueError("bounds must have N_d entries")
+        _check(_lib.sq_set_bounds(self._ctx, _dptr(self._lmin), _dptr(self._lmax), self._stream_ptr()))
+
+    def moments(self, out=None):
+        torch = self.torch
+        if out is None:
+            out = torch.empty((self.nd, self.npl + 1), dtype=torch.float64, device=self.device)
+        _check(_lib.sq_moments(self._ctx, _dptr(out), self._stream_ptr()))
+        return out
+
+    def fermi_level(self, moments, n_electrons) -> float:
+        mu = ct.c_double()
+        _check(_lib.sq_fermi_level(self._ctx, _dptr(moments), float(n_electrons), ct.byref(mu),
+                                   self._stream_ptr()))
+        return mu.value
+
+    def density_energy(self, moments, mu, rho=None):
+        torch = self.torch
+        if rho is None:
+            rho = torch.empty(self.nd, dtype=torch.float64, device=self.device)
+        e = (ct.c_double * 4)()
+        _check(_lib.sq_density_energy(self._ctx, _dptr(moments), float(mu), _dptr(rho), e,
+                                      self._stream_ptr()))
+        return rho, np.array(list(e))
+
+    def scf_pass(self, n_electrons):
+        """bounds -> moments -> Fermi level -> density and energies (fixed V_eff)."""
+        self.spectral_bounds()
+        mom = self.moments()
+        mu = self.fermi_level(mom, n_electrons)
+        rho, e = self.density_energy(mom, mu)
+        return mom, mu, rho, e

@@ -1,0 +1,215 @@
+"""GPU parity: libsq (HIP, gfx950) against the FP64 CPU oracle, through the C ABI.
+
+Tolerances (FP64 path): moments |d rho^j| <= 1e-10 (moments are bounded by 1),
+density max|d rho| / max rho <= 1e-10, energies 1e-10 relative.  Moment parity
+is checked on bounds injected from the other side, because Ritz values of two
+independent FP64 Lanczos runs agree only to rounding amplified by the
+recurrence (bounds themselves: 1e-8 relative).  Mixed precision: density
+1e-5 relative and energies 1e-6 Ha/atom against the FP64 oracle.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_07913_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_07913_amd import sq
+    sq.load_library()
+    torch.cuda.set_device(0)
+
+
+def _sq():
+    from paper_1708_07913_amd import sq
+    return sq
+
+
+def _pair(wl, precision=None, **kw):
+    sq = _sq()
+    V = wl.veff()
+    ref = oracle.Oracle.from_workload(wl, veff=V)
+    g = sq.SQ.from_workload(wl, veff=torch.from_numpy(V).cuda(),
+                            precision=sq.FP64 if precision is None else precision, **kw)
+    return V, ref, g
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def test_tiny_cell_fp64_pipeline():
+    wl = W.tiny_cell()
+    print(f"case {wl.name}", flush=True)
+    V, ref, g = _pair(wl)
+    lmin, lmax = ref.bounds()
+    mom_ref = ref.moments(lmin, lmax)
+    mu_ref, _ = ref.fermi_level(lmin, lmax, mom_ref, wl.n_electrons)
+    rho_ref, e_ref = ref.density_energy(lmin, lmax, mom_ref, mu_ref)
+    # bounds
+    glo, ghi = g.spectral_bounds()
+    scale = np.abs(lmax).max()
+    assert np.abs(_np(glo) - lmin).max() < 1e-8 * scale
+    assert np.abs(_np(ghi) - lmax).max() < 1e-8 * scale
+    # moments on the oracle's bounds
+    g.set_bounds(torch.from_numpy(lmin), torch.from_numpy(lmax))
+    mom = g.moments()
+    m = _np(mom)
+    assert np.all(m[:, 0] == 1.0)
+    assert np.abs(m - mom_ref).max() < 1e-10
+    # Fermi level and density
+    mu = g.fermi_level(mom, wl.n_electrons)
+    assert abs(mu - mu_ref) < 1e-10
+    rho, e = g.density_energy(mom, mu_ref)
+    r = _np(rho)
+    assert np.abs(r - rho_ref).max() < 1e-10 * rho_ref.max()
+    assert np.abs(e - e_ref).max() < 1e-10 * np.abs(e_ref).max()
+    assert abs(e[3] - wl.n_electrons) < 1e-10 * wl.n_electrons
+    # density at its own mu satisfies the electron count
+    rho2, e2 = g.density_energy(mom, mu)
+    assert abs(e2[3] - wl.n_electrons) < 1e-11 * wl.n_electrons
+
+
+EDGE_CASES = {
+    # name: (cells, a, A, seed, h, rcut, npl, kT_eV, fd_order, natom_keep)
+    "cube3_npl8": (1, 8.0, 0.1, 1, 0.5, 0.5, 8, 1.0, 12, None),
+    "fd2_cube7": (1, 6.0, 0.2, 7, 0.5, 1.5, 12, 2.0, 2, None),
+    "no_atoms_cube9": (1, 6.5, 0.0, 0, 0.5, 2.0, 16, 1.0, 12, 0),
+    "one_atom_fd8_cube15": (1, 10.0, 0.3, 3, 0.5, 3.5, 16, 3.0, 8, 1),
+    "ragged_n13_cube11": (1, 6.5, 0.1, 9, 0.5, 2.5, 20, 1.0, 12, None),
+    "npl4": (1, 8.0, 0.1, 2, 0.5, 1.0, 4, 5.0, 12, None),
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGE_CASES))
+def test_edge_cases_moments_and_bounds(name):
+    cells, a, A, seed, h, rc, npl, kT, fd, keep = EDGE_CASES[name]
+    wl = W.fcc_workload(name, cells, a, A, seed, h, rc, npl, kT, fd_order=fd)
+    if keep is not None:
+        wl.atoms = wl.atoms[:keep]
+        wl.kb = wl.kb[:keep]
+        wl.n_electrons = 0.25 * (wl.cell / wl.h_eff) ** 3
+    print(f"case {name} n={wl.n}", flush=True)
+    V, ref, g = _pair(wl)
+    lmin, lmax = ref.bounds()
+    glo, ghi = g.spectral_bounds()
+    scale = np.abs(lmax).max()
+    assert np.abs(_np(glo) - lmin).max() < 1e-8 * scale
+    assert np.abs(_np(ghi) - lmax).max() < 1e-8 * scale
+    g.set_bounds(torch.from_numpy(lmin), torch.from_numpy(lmax))
+    m = _np(g.moments())
+    mom_ref = ref.moments(lmin, lmax)
+    assert np.abs(m - mom_ref).max() < 1e-10
+
+
+def test_mixed_precision_tiny_cell():
+    sq = _sq()
+    wl = W.tiny_cell()
+    print(f"case {wl.name} mixed", flush=True)
+    V, ref, g = _pair(wl, precision=sq.FP32_MIXED)
+    lmin, lmax = ref.bounds()
+    mom_ref = ref.moments(lmin, lmax)
+    mu_ref, _ = ref.fermi_level(lmin, lmax, mom_ref, wl.n_electrons)
+    rho_ref, e_ref = ref.density_energy(lmin, lmax, mom_ref, mu_ref)
+    # mixed recurrence on the oracle's bounds, density at the oracle's mu
+    g.set_bounds(torch.from_numpy(lmin), torch.from_numpy(lmax))
+    mom = g.moments()
+    rho, e = g.density_energy(mom, mu_ref)
+    err = np.abs(_np(rho) - rho_ref).max() / rho_ref.max()
+    print(f"mixed rho rel err {err:.3e}  dE_band/atom {(e[0]-e_ref[0])/wl.natom:.2e}", flush=True)
+    assert err < 1e-5
+    assert abs(e[0] - e_ref[0]) / wl.natom < 1e-6
+    assert abs(e[2] - e_ref[2]) / wl.natom < 1e-6
+    # full mixed pass with its own (FP64) bounds and Fermi level
+    mom2, mu2, rho2, e2 = g.scf_pass(wl.n_electrons)
+    assert abs(e2[3] - wl.n_electrons) < 1e-9 * wl.n_electrons
+    err2 = np.abs(_np(rho2) - rho_ref).max() / rho_ref.max()
+    assert err2 < 1e-5, err2
+
+
+@pytest.mark.parametrize("kT,npl", [(0.5, 32), (5.0, 32), (0.5, 96), (5.0, 96)])
+def test_mixed_precision_sweep_corners(kT, npl):
+    sq = _sq()
+    wl = W.tiny_cell(precision="mixed", npl=npl, kT_eV=kT)
+    print(f"case mixed kT={kT} npl={npl}", flush=True)
+    V, ref, g = _pair(wl, precision=sq.FP32_MIXED)
+    lmin, lmax = ref.bounds()
+    mom_ref = ref.moments(lmin, lmax)
+    mu_ref, _ = ref.fermi_level(lmin, lmax, mom_ref, wl.n_electrons)
+    rho_ref, e_ref = ref.density_energy(lmin, lmax, mom_ref, mu_ref)
+    g.set_bounds(torch.from_numpy(lmin), torch.from_numpy(lmax))
+    rho, e = g.density_energy(g.moments(), mu_ref)
+    err = np.abs(_np(rho) - rho_ref).max() / rho_ref.max()
+    assert err < 1e-5, err
+    assert abs(e[2] - e_ref[2]) / wl.natom < 1e-6
+
+
+def _sampled_parity(wl, nsample, seed=0):
+    V, ref, g = _pair(wl)
+    nd = g.nd
+    rng = np.random.default_rng(seed)
+    nodes = np.unique(np.concatenate([[0, 1, nd // 2, nd - 2, nd - 1],
+                                      rng.choice(nd, nsample, replace=False)]))
+    glo, ghi = g.spectral_bounds()
+    mom = g.moments()
+    mu = g.fermi_level(mom, wl.n_electrons)
+    rho, e = g.density_energy(mom, mu)
+    glo, ghi, m, r = _np(glo), _np(ghi), _np(mom), _np(rho)
+    # bounds of the sampled nodes
+    olo, ohi = ref.bounds(nodes)
+    scale = np.abs(ohi).max()
+    assert np.abs(glo[nodes] - olo).max() < 1e-8 * scale
+    assert np.abs(ghi[nodes] - ohi).max() < 1e-8 * scale
+    # moments of the sampled nodes on the GPU's bounds
+    mom_ref = ref.moments(glo[nodes], ghi[nodes], nodes=nodes)
+    assert np.abs(m[nodes] - mom_ref).max() < 1e-10
+    # density of the sampled nodes at the GPU's Fermi level
+    rho_ref, _ = ref.density_energy(glo[nodes], ghi[nodes], mom_ref, mu)
+    assert np.abs(r[nodes] - rho_ref).max() < 1e-10 * r.max()
+    # properties at full size
+    assert abs(e[3] - wl.n_electrons) < 1e-10 * wl.n_electrons
+    assert np.all(m[:, 0] == 1.0) and np.abs(m).max() <= 1.0 + 1e-10
+    assert abs(e[2] - (e[0] + e[1])) < 1e-12 * abs(e[2])
+    return mu, e
+
+
+def test_paper_size_cell_sampled():
+    wl = W.paper_size_cell()
+    print(f"case {wl.name} n={wl.n}", flush=True)
+    _sampled_parity(wl, 24)
+
+
+def test_large_cell_sampled():
+    wl = W.large_cell()
+    print(f"case {wl.name} n={wl.n}", flush=True)
+    _sampled_parity(wl, 12, seed=1)
+
+
+def test_error_paths():
+    sq = _sq()
+    wl = W.tiny_cell()
+    V, ref, g = _pair(wl)
+    with pytest.raises(sq.SQError) as ei:
+        g.moments()
+    assert ei.value.code == -4                     # bounds not computed yet
+    lmin, lmax = ref.bounds()
+    g.set_bounds(torch.from_numpy(lmin), torch.from_numpy(lmax))
+    mom = g.moments()
+    with pytest.raises(sq.SQError) as ei:
+        g.fermi_level(mom, 2.0 * g.nd)
+    assert ei.value.code == -1
+    # bounds far too tight: the scaled spectrum leaves [-1, 1]
+    mid = 0.5 * (lmin + lmax)
+    g.set_bounds(torch.from_numpy(mid - 0.1), torch.from_numpy(mid + 0.1))
+    with pytest.raises(sq.SQError) as ei:
+        g.moments()
+    assert ei.value.code == -6
