@@ -1,0 +1,195 @@
+"""Benchmark: one SQ density/energy pass (SCF iteration at fixed V_eff) per step.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload paper|large|tiny]
+
+A step runs every stage of the hot path on the resident inputs: Lanczos
+spectral bounds -> Chebyshev moments -> Fermi level -> density and energies.
+The default workload is the 256-atom paper-size cell (78^3 grid, 31^3
+regions, n_pl = 48, FP64).  One JSON line is printed with the throughput in
+grid-point x Chebyshev-step per second over whole steps, the roofline of the
+dominant kernel (HIP events on the working stream), the FP32-mixed pass and
+the FP64 CPU oracle timed on a bounded node sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SQ grid-pt*Chebyshev-steps/s & s/SCF iter, FP64 vs FP32-mixed at rho err 1e-5"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1708_07913_amd", "csrc", "sq_kernels.hip")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def workload(name):
+    from paper_1708_07913_amd import workloads as W
+    return {"paper": W.paper_size_cell, "large": W.large_cell, "tiny": W.tiny_cell}[name]()
+
+
+def traffic_from_profiles(kernel_key: str, workload_name: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, only if
+    they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        ent = data.get(f"{kernel_key}:{workload_name}")
+        if ent and ent.get("kernel_source_sha") == kernel_hash():
+            return ent["bytes_per_launch"]
+    except (ValueError, KeyError):
+        return None
+    return None
+
+
+def run_gpu(wl, steps, warmup, precision):
+    import torch
+    from paper_1708_07913_amd import sq
+
+    V = torch.from_numpy(wl.veff()).cuda()
+    g = sq.SQ.from_workload(wl, veff=V, precision=precision)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        g.scf_pass(wl.n_electrons)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    out = None
+    t0 = time.perf_counter()
+    for s in range(steps):
+        e = ev[s]
+        e[0].record(stream)
+        g.spectral_bounds()
+        e[1].record(stream)
+        mom = g.moments()
+        e[2].record(stream)
+        mu = g.fermi_level(mom, wl.n_electrons)
+        e[3].record(stream)
+        rho, en = g.density_energy(mom, mu)
+        e[4].record(stream)
+        out = (mom, mu, rho, en)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases = np.array([[ev[s][i].elapsed_time(ev[s][i + 1]) for i in range(4)] for s in range(steps)])
+    return g, out, wall, phases.mean(0)  # ms per phase
+
+
+def cpu_baseline(wl, budget_s=20.0):
+    """The FP64 oracle on a bounded node sample of the same workload (bounds +
+    moments, the per-node work of a step), scaled to node-steps per second."""
+    import oracle
+    V = wl.veff()
+    o = oracle.Oracle.from_workload(wl, veff=V)
+    rng = np.random.default_rng(0)
+    count, elapsed = 8, 0.0
+    while True:
+        nodes = rng.choice(o.nd, count, replace=False)
+        t = time.perf_counter()
+        lo, hi = o.bounds(nodes)
+        o.moments(lo, hi, nodes=nodes)
+        elapsed = time.perf_counter() - t
+        if elapsed >= budget_s / 2 or count >= o.nd:
+            break
+        count = int(min(o.nd, max(2 * count, count * (budget_s / 1.5) / max(elapsed, 1e-3))))
+    rate = count * (wl.npl // 2) / elapsed
+    return {"value": rate, "unit": "grid-pt*Chebyshev-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{count} random nodes of {o.nd} (seed 0): Lanczos bounds + moments, {elapsed:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="paper", choices=["paper", "large", "tiny"])
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1708_07913_amd import sq
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    wl = workload(args.workload)
+    print(f"[bench] {wl.name}: n={wl.n} natom={wl.natom} npl={wl.npl}", file=sys.stderr, flush=True)
+
+    g, (mom, mu, rho, en), wall, ph = run_gpu(wl, args.steps, args.warmup, sq.FP64)
+    nd, S = g.nd, wl.npl // 2
+    C = 2 * g.m + 1
+    ns = C ** 3
+    ms_step = 1e3 * wall / args.steps
+    value = nd * S / (wall / args.steps)
+    print(f"[bench] fp64: {ms_step:.1f} ms/step phases(ms) bounds {ph[0]:.1f} moments {ph[1]:.1f} "
+          f"fermi {ph[2]:.1f} density {ph[3]:.1f}", file=sys.stderr, flush=True)
+
+    # dominant kernel and its roofline (algorithmic bytes: 3 N_s words per node-step)
+    lanczos_bytes = nd * 50 * 3 * ns * 8
+    moments_bytes = nd * S * 3 * ns * 8
+    if ph[0] >= ph[1]:
+        kname, kbytes, kms = "lanczos_kernel", lanczos_bytes, ph[0]
+    else:
+        kname, kbytes, kms = "moments_kernel", moments_bytes, ph[1]
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kname, wl.name),
+            "kernel": kname, "algorithmic_bytes_per_launch": kbytes, "avg_launch_ms": kms}
+
+    rec = {"metric": METRIC, "value": value, "unit": "grid-pt*Chebyshev-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded FCC Al-like cell, Gaussian-well V_eff, s-type KB projectors)",
+           "config": {"workload": wl.name, "n_grid": wl.n, "n_nodes": nd, "region_points": ns,
+                      "npl": wl.npl, "n_lanczos": 50, "natom": wl.natom, "kT_eV": wl.kT_eV,
+                      "parallelism": "single GPU"},
+           "s_per_scf": wall / args.steps,
+           "moments_node_steps_per_s": nd * S / (ph[1] * 1e-3),
+           "phase_ms": {"bounds": ph[0], "moments": ph[1], "fermi": ph[2], "density": ph[3]},
+           "roofline": roof,
+           "electron_count": float(en[3]), "mu": mu}
+
+    if not args.no_mixed:
+        gm, (mom_m, mu_m, rho_m, en_m), wall_m, ph_m = run_gpu(wl, args.steps, args.warmup, sq.FP32_MIXED)
+        # accuracy of the mixed recurrence against FP64 on identical bounds and Fermi level
+        lmin, lmax = g.spectral_bounds()
+        gm.set_bounds(lmin, lmax)
+        rho64, e64 = g.density_energy(mom, mu)
+        rhom, em = gm.density_energy(gm.moments(), mu)
+        torch.cuda.synchronize()
+        r64, rm = rho64.cpu().numpy(), rhom.cpu().numpy()
+        rec["mixed"] = {"ms_per_step": 1e3 * wall_m / args.steps, "value": nd * S / (wall_m / args.steps),
+                        "moments_node_steps_per_s": nd * S / (ph_m[1] * 1e-3),
+                        "phase_ms": {"bounds": ph_m[0], "moments": ph_m[1], "fermi": ph_m[2],
+                                     "density": ph_m[3]},
+                        "rho_max_rel_err_vs_fp64": float(np.abs(rm - r64).max() / r64.max()),
+                        "E_band_err_Ha_per_atom": float(abs(em[0] - e64[0]) / wl.natom),
+                        "F_err_Ha_per_atom": float(abs(em[2] - e64[2]) / wl.natom),
+                        "electron_count_err": float(abs(en_m[3] - wl.n_electrons))}
+        print(f"[bench] mixed: {rec['mixed']['ms_per_step']:.1f} ms/step, rho err "
+              f"{rec['mixed']['rho_max_rel_err_vs_fp64']:.2e}", file=sys.stderr, flush=True)
+
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

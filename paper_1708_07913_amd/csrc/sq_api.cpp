@@ -60,6 +60,8 @@ struct sq_ctx {
     double start_norm = 0;
     int device = 0;
     int nwg_lanczos = 0, nwg_moments = 0, nwg_slots = 0;
+    int nch = 2;        // projector chains per cube column (max sphere overlap depth)
+    int max_overlap = 0;
     size_t off_atoms = 0, off_runs = 0, off_pvals = 0, off_chi = 0, off_zeta = 0, off_ctab = 0,
            off_rk = 0, off_W = 0, off_part = 0, off_scal = 0, off_flags = 0, off_v32 = 0,
            off_slots = 0, total = 0;
@@ -197,6 +199,7 @@ sq::RecurrenceArgs recurrence_args(sq_ctx *c) {
     a.slots = c->ws + c->off_slots;
     a.slot_elems = c->ns;
     a.flags = c->at<int>(c->off_flags);
+    a.nch = c->nch;
     a.n_lanczos = c->opt.n_lanczos;
     a.start_norm = c->start_norm;
     a.margin = c->opt.margin;
@@ -214,9 +217,9 @@ int pick_workgroups(sq_ctx *c) {
     if (rc) return rc;
     const bool mixed = c->opt.precision == SQ_FP32_MIXED;
     int bl = 0, bm = 0;
-    rc = hip_check(sq::recurrence_occupancy(c->C, true, false, &bl), "occupancy (Lanczos)");
+    rc = hip_check(sq::recurrence_occupancy(c->C, true, false, c->nch, &bl), "occupancy (Lanczos)");
     if (rc) return rc;
-    rc = hip_check(sq::recurrence_occupancy(c->C, false, mixed, &bm), "occupancy (moments)");
+    rc = hip_check(sq::recurrence_occupancy(c->C, false, mixed, c->nch, &bm), "occupancy (moments)");
     if (rc) return rc;
     if (bl < 1 || bm < 1) return fail(SQ_EDEVICE, "recurrence kernel does not fit on a compute unit");
     auto round8 = [](long long v) { return int(std::max<long long>(8, (v + 7) / 8 * 8)); };
@@ -383,6 +386,26 @@ int sq_setup(sq_ctx **ctx, double cell, double h, int fd_order, double rcut, int
                 return fail(SQ_EINVAL, "atom position too far from the cell");
             int rc2 = build_atom_table(c.get(), R, sig, rc, gam);
             if (rc2) return rc2;
+        }
+        // deepest overlap of projector spheres at a grid point (periodic count of
+        // atom images): the per-column run chains the kernels must carry
+        {
+            std::vector<int> depth(size_t(c->nd), 0);
+            const long long n = c->n;
+            auto wrap = [n](long long v) { long long r = v % n; return r < 0 ? r + n : r; };
+            for (const auto &at : c->atoms)
+                for (int r = 0; r < at.nrun; ++r) {
+                    const sq::RunDev &run = c->runs[size_t(at.run0 + r)];
+                    const long long gx = wrap(at.bx + run.dx), gy = wrap(at.by + run.dy);
+                    for (int k = 0; k < run.len; ++k) {
+                        const long long gz = wrap(at.bz + run.dz0 + k);
+                        const int d = ++depth[size_t(gx + n * (gy + n * gz))];
+                        if (d > c->max_overlap) c->max_overlap = d;
+                    }
+                }
+            if (c->max_overlap > 4)
+                return fail(SQ_ECAPACITY, "more than four projector spheres overlap at a grid point");
+            c->nch = c->max_overlap > 2 ? 4 : 2;
         }
         // discrete-orthogonality table on N_q = n_pl + 1 Chebyshev-Gauss nodes
         c->ctab.assign(size_t(c->nq) * c->nq, 0.0);

@@ -31,7 +31,7 @@ struct RunDev {
 enum Flags : int {
     kFlagImages = 1,    // more than kMaxImages images in a region
     kFlagRuns = 2,      // more projector runs than the per-node table holds
-    kFlagOverlap = 4,   // more than two projector spheres overlap at a point
+    kFlagOverlap = 4,   // more projector spheres overlap at a point than chains exist
     kFlagBounds = 8,    // a moment left [-1, 1]
     kFlagLanczos = 16,  // non-finite Lanczos coefficient
 };
@@ -54,6 +54,7 @@ struct RecurrenceArgs {
     void *slots;            // nwg slots of C^3 elements
     long long slot_elems;
     int *flags;
+    int nch;                // projector chains per column: 2 or 4 (max sphere overlap depth)
     int n_lanczos;
     double start_norm;      // norm of the unnormalised Lanczos start vector
     double margin;
@@ -64,7 +65,7 @@ struct RecurrenceArgs {
 hipError_t launch_lanczos(const RecurrenceArgs &a, int nwg, hipStream_t s);
 hipError_t launch_moments(const RecurrenceArgs &a, bool mixed, int nwg, hipStream_t s);
 int recurrence_block(int C);
-hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int *blocks_per_cu);
+hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int nch, int *blocks_per_cu);
 hipError_t launch_set_bounds(const double *lmin, const double *lmax, double *chi, double *zeta,
                              long long nd, double margin, hipStream_t s);
 hipError_t launch_to_fp32(const double *src, float *dst, long long n, hipStream_t s);

@@ -49,13 +49,13 @@ struct Shape {
 constexpr unsigned kSentinelX = (0xFEu << 16) | (0xFFu << 8);
 constexpr unsigned kIdleOffset = 0x7FFFFF00u;  // beyond every buffer: loads read 0, stores drop
 
-template <int C, typename T>
+template <int C, typename T, int NCH>
 struct Lds {
     T plane[2][Shape<C>::PLANE];
     uint2 runs[Shape<C>::MAXRUNS + 1];
     int col_start[Shape<C>::CC + 1];
     int col_fill[Shape<C>::CC];
-    int col_na[Shape<C>::CC];
+    int col_off[Shape<C>::CC][NCH];  // first record of each chain, relative to col_start
     int img_atom[kMaxImages];
     int img_lb[kMaxImages][3];
     int img_prefix[kMaxImages + 1];
@@ -69,7 +69,7 @@ struct Lds {
     int scan_tot[Shape<C>::NW];
     int ni;
     int bad;
-    int has_b;
+    int nch;  // chains needed by this region (max sphere overlap depth, >= 1)
 };
 
 struct LanczosLds {
@@ -131,8 +131,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum of (a, b) over the workgroup; the result is returned to every thread.
-template <int C, typename T>
-__device__ __forceinline__ void block_sum2(Lds<C, T> &L, double &a, double &b, int tid) {
+template <int C, typename T, int NCH>
+__device__ __forceinline__ void block_sum2(Lds<C, T, NCH> &L, double &a, double &b, int tid) {
     constexpr int NW = Shape<C>::NW;
     a = wave_sum(a);
     b = wave_sum(b);
@@ -164,7 +164,7 @@ __device__ __forceinline__ double unit_from_seed(unsigned long long seed) {
 
 __device__ __forceinline__ unsigned run_key(uint2 r, bool with_chain) {
     // (chain, z_first, image slot)
-    return (with_chain ? (((r.x >> 24) & 1u) << 16) : 0u) | (((r.x >> 8) & 0xFFu) << 8) | (r.x & 0xFFu);
+    return (with_chain ? (((r.x >> 24) & 3u) << 16) : 0u) | (((r.x >> 8) & 0xFFu) << 8) | (r.x & 0xFFu);
 }
 
 __device__ void sort_runs(uint2 *runs, int b, int e, bool with_chain) {
@@ -185,14 +185,14 @@ __device__ void sort_runs(uint2 *runs, int b, int e, bool with_chain) {
 // cube column, the clipped z-runs of their spheres split into two chains of
 // non-overlapping runs (a second chain exists only where two spheres overlap).
 // ---------------------------------------------------------------------------
-template <int C, typename T>
-__device__ void setup_region(const RecurrenceArgs &A, Lds<C, T> &L, int qi, int qj, int qk, int tid) {
+template <int C, typename T, int NCH>
+__device__ void setup_region(const RecurrenceArgs &A, Lds<C, T, NCH> &L, int qi, int qj, int qk, int tid) {
     using S = Shape<C>;
     const int n = A.n, m = A.m;
     if (tid == 0) {
         L.ni = 0;
         L.bad = 0;
-        L.has_b = 0;
+        L.nch = 1;
         L.runs[S::MAXRUNS] = make_uint2(kSentinelX, 0u);
     }
     for (int i = tid; i < 2 * S::PLANE; i += S::BLOCK) (&L.plane[0][0])[i] = T(0);
@@ -294,33 +294,49 @@ __device__ void setup_region(const RecurrenceArgs &A, Lds<C, T> &L, int qi, int 
         if (tid <= S::CC) L.col_start[tid] = 0;
         __syncthreads();
     }
-    // per column: sort by z_first, split into two chains of disjoint runs,
-    // and order chain 0 before chain 1
+    // per column: sort by z_first, split first-fit into chains of disjoint runs
+    // (as many as spheres overlap at one point), chain 0 first
     if (tid < S::CC) {
         const int b = L.col_start[tid], e = L.col_start[tid + 1];
         sort_runs(L.runs, b, e, false);
-        int last0 = -1, last1 = -1, na = 0;
-        bool two = false;
+        int last[NCH], cnt[NCH];
+#pragma unroll
+        for (int ci = 0; ci < NCH; ++ci) {
+            last[ci] = -1;
+            cnt[ci] = 0;
+        }
+        int used = 1;
         for (int i = b; i < e; ++i) {
             uint2 r = L.runs[i];
             const int zf = (int)((r.x >> 8) & 0xFFu), zl = (int)((r.x >> 16) & 0xFFu);
-            if (zf > last0) {
-                last0 = zl;
-                ++na;
-            } else if (zf > last1) {
-                last1 = zl;
-                r.x |= 1u << 24;
-                two = true;
-            } else {
+            int c = -1;
+#pragma unroll
+            for (int ci = 0; ci < NCH; ++ci)
+                if (c < 0 && zf > last[ci]) c = ci;
+            if (c < 0) {
                 atomicOr(A.flags, kFlagOverlap);
+                c = NCH - 1;
             }
+#pragma unroll
+            for (int ci = 0; ci < NCH; ++ci)
+                if (c == ci) {
+                    last[ci] = zl;
+                    ++cnt[ci];
+                }
+            if (c + 1 > used) used = c + 1;
+            r.x |= (unsigned)c << 24;
             L.runs[i] = r;
         }
-        if (two) {
+        if (used > 1) {
             sort_runs(L.runs, b, e, true);
-            L.has_b = 1;
+            atomicMax(&L.nch, used);
         }
-        L.col_na[tid] = na;
+        int off = 0;
+#pragma unroll
+        for (int ci = 0; ci < NCH; ++ci) {
+            L.col_off[tid][ci] = off;
+            off += cnt[ci];
+        }
     }
     __syncthreads();
 }
@@ -361,14 +377,17 @@ struct Chain {
     }
 };
 
-template <int C, typename T>
-__device__ __forceinline__ void chains_start(const Lds<C, T> &L, int tid, bool active, Chain &ca, Chain &cb) {
+template <int C, typename T, int NCH>
+__device__ __forceinline__ void chains_start(const Lds<C, T, NCH> &L, int tid, bool active, Chain (&ch)[NCH]) {
     constexpr int SENT = Shape<C>::MAXRUNS;
     const int b = active ? L.col_start[tid] : 0;
     const int e = active ? L.col_start[tid + 1] : 0;
-    const int na = active ? L.col_na[tid] : 0;
-    ca.start(L.runs, b, b + na, SENT);
-    cb.start(L.runs, b + na, e, SENT);
+#pragma unroll
+    for (int ci = 0; ci < NCH; ++ci) {
+        const int s0 = b + (active ? L.col_off[tid][ci] : 0);
+        const int s1 = ci + 1 < NCH ? b + (active ? L.col_off[tid][ci + 1] : 0) : e;
+        ch[ci].start(L.runs, s0, s1, SENT);
+    }
 }
 
 __device__ __forceinline__ void node_coords(long long q, int n, int &qi, int &qj, int &qk) {
@@ -378,22 +397,22 @@ __device__ __forceinline__ void node_coords(long long q, int n, int &qi, int &qj
 }
 
 // Projector dots of the register column tv: s[dst][I] += p_I . tv
-template <int C, typename T, typename V>
-__device__ __forceinline__ void projector_dots(Lds<C, T> &L, __amdgpu_buffer_rsrc_t pvr, const V (&tv)[C],
-                                               int dst, int tid, bool active, bool has_b) {
+template <int C, typename T, int NCH, typename V>
+__device__ __forceinline__ void projector_dots(Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr, const V (&tv)[C],
+                                               int dst, int tid, bool active, int nch) {
     constexpr int SENT = Shape<C>::MAXRUNS;
-    Chain ca, cb;
-    chains_start(L, tid, active, ca, cb);
+    Chain ch[NCH];
+    chains_start(L, tid, active, ch);
 #pragma unroll
     for (int z = 0; z < C; ++z) {
         const double t = (double)tv[z];
-        ca.acc += ca.value(pvr, z) * t;
-        pin(ca.acc);
-        ca.finish(L.s[dst], z, L.runs, SENT);
-        if (has_b) {
-            cb.acc += cb.value(pvr, z) * t;
-            pin(cb.acc);
-            cb.finish(L.s[dst], z, L.runs, SENT);
+#pragma unroll
+        for (int ci = 0; ci < NCH; ++ci) {
+            if (ci == 0 || ci < nch) {
+                ch[ci].acc += ch[ci].value(pvr, z) * t;
+                pin(ch[ci].acc);
+                ch[ci].finish(L.s[dst], z, L.runs, SENT);
+            }
         }
     }
     __syncthreads();
@@ -405,12 +424,12 @@ __device__ __forceinline__ void projector_dots(Lds<C, T> &L, __amdgpu_buffer_rsr
 //   rho^j = t^j[q] (j <= n_pl/2), rho^{2k} = 2 t^k.t^k - rho^0,
 //   rho^{2k-1} = 2 t^k.t^{k-1} - rho^1 (k > n_pl/4).
 // ---------------------------------------------------------------------------
-template <int C, typename T>
+template <int C, typename T, int NCH>
 __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs A) {
     using S = Shape<C>;
     constexpr int MC = (C - 1) / 2;
     constexpr int SENT = S::MAXRUNS;
-    __shared__ Lds<C, T> L;
+    __shared__ Lds<C, T, NCH> L;
     const int tid = threadIdx.x;
     const bool active = tid < S::CC;
     const int x = active ? tid % C : 0, y = active ? tid / C : 0;
@@ -435,7 +454,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
         node_coords(q, n, qi, qj, qk);
         setup_region(A, L, qi, qj, qk, tid);
         const int ni = L.ni < kMaxImages ? L.ni : kMaxImages;
-        const bool has_b = L.has_b != 0;
+        const int nch = L.nch;
         const unsigned zbase = (unsigned)pmod(qk - A.m, n);
         const double chi = uniform(A.chi[q]), zeta = uniform(A.zeta[q]);
         const double invz = uniform(1.0 / zeta);
@@ -452,15 +471,15 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
         for (int z = 0; z < C; ++z) tv[z] = T((is_centre && z == MC) ? 1 : 0);
         if (tid == 0) mrow[0] = 1.0;
         int cur = 0;
-        projector_dots(L, pvr, tv, cur, tid, active, has_b);
+        projector_dots(L, pvr, tv, cur, tid, active, nch);
 
         for (int k = 0; k < half; ++k) {
             const double al = k == 0 ? 1.0 : 2.0;
             const double scale = uniform(al * invz);
             for (int i = tid; i < kMaxImages; i += S::BLOCK)
                 L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur][i] : 0.0;
-            Chain ca, cb;
-            chains_start(L, tid, active, ca, cb);
+            Chain ch[NCH];
+            chains_start(L, tid, active, ch);
             double *snext = L.s[cur ^ 1];
             double d1 = 0.0, d2 = 0.0;
             unsigned zb = zbase;
@@ -489,12 +508,15 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
                 }
                 const double tz = (double)tv[z];
                 const double u = acc + (vz + c0) * invz * tz;
-                const double pa = ca.value(pvr, z);
-                double nvd = al * u + L.cs[ca.sl] * pa - tprev;
-                double pb = 0.0;
-                if (has_b) {
-                    pb = cb.value(pvr, z);
-                    nvd += L.cs[cb.sl] * pb;
+                double pv[NCH];
+                double nvd = al * u - tprev;
+#pragma unroll
+                for (int ci = 0; ci < NCH; ++ci) {
+                    pv[ci] = 0.0;
+                    if (ci == 0 || ci < nch) {
+                        pv[ci] = ch[ci].value(pvr, z);
+                        nvd += L.cs[ch[ci].sl] * pv[ci];
+                    }
                 }
                 const T nvt = T(nvd);
                 nvd = (double)nvt;
@@ -504,13 +526,13 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
                 d2 += nvd * tz;
                 pin(d1);
                 pin(d2);
-                ca.acc += pa * nvd;
-                pin(ca.acc);
-                ca.finish(snext, z, L.runs, SENT);
-                if (has_b) {
-                    cb.acc += pb * nvd;
-                    pin(cb.acc);
-                    cb.finish(snext, z, L.runs, SENT);
+#pragma unroll
+                for (int ci = 0; ci < NCH; ++ci) {
+                    if (ci == 0 || ci < nch) {
+                        ch[ci].acc += pv[ci] * nvd;
+                        pin(ch[ci].acc);
+                        ch[ci].finish(snext, z, L.runs, SENT);
+                    }
                 }
                 if (z == MC && is_centre) {
                     mrow[k + 1] = nvd;
@@ -576,12 +598,12 @@ __device__ double sturm_bisect(int k, const double *a, const double *b, int targ
     return hi;
 }
 
-template <int C>
+template <int C, int NCH>
 __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs A) {
     using S = Shape<C>;
     using T = double;
     constexpr int SENT = S::MAXRUNS;
-    __shared__ Lds<C, T> L;
+    __shared__ Lds<C, T, NCH> L;
     __shared__ LanczosLds LL;
     const int tid = threadIdx.x;
     const bool active = tid < S::CC;
@@ -609,7 +631,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
         node_coords(q, n, qi, qj, qk);
         setup_region(A, L, qi, qj, qk, tid);
         const int ni = L.ni < kMaxImages ? L.ni : kMaxImages;
-        const bool has_b = L.has_b != 0;
+        const int nch = L.nch;
         const unsigned zbase = (unsigned)pmod(qk - A.m, n);
         const unsigned vcol = active ? (unsigned)(pmod(qi - A.m + x, n) + n * pmod(qj - A.m + y, n)) * 8u : kIdleOffset;
 
@@ -618,7 +640,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
         for (int z = 0; z < C; ++z)
             tv[z] = active ? (unit_from_seed((unsigned long long)(x + C * (y + C * z))) - 0.5) / A.start_norm : 0.0;
         int cur = 0;
-        projector_dots(L, pvr, tv, cur, tid, active, has_b);
+        projector_dots(L, pvr, tv, cur, tid, active, nch);
 
         double bprev = 0.0, gersh = 0.0;
         int ksteps = kmax;
@@ -626,8 +648,8 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
             // w = H v - beta_{j-1} v_{j-1};  slot <- v;  alpha = w . v
             for (int i = tid; i < kMaxImages; i += S::BLOCK)
                 L.cs[i] = i < ni ? L.img_coef[i] * L.s[cur][i] : 0.0;
-            Chain ca, cb;
-            chains_start(L, tid, active, ca, cb);
+            Chain ch[NCH];
+            chains_start(L, tid, active, ch);
             unsigned zb = zbase;
             asm volatile("" : "+s"(zb));
             double wv[C];
@@ -654,10 +676,13 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
                     acc += kw[d] * (xs + ys + zs);
                 }
                 double u = acc + (vz + kin0) * tv[z];
-                u += L.cs[ca.sl] * ca.value(pvr, z);
-                if (has_b) u += L.cs[cb.sl] * cb.value(pvr, z);
-                ca.finish(L.s[cur ^ 1], z, L.runs, SENT);   // advance only; accumulators stay 0
-                if (has_b) cb.finish(L.s[cur ^ 1], z, L.runs, SENT);
+#pragma unroll
+                for (int ci = 0; ci < NCH; ++ci) {
+                    if (ci == 0 || ci < nch) {
+                        u += L.cs[ch[ci].sl] * ch[ci].value(pvr, z);
+                        ch[ci].finish(L.s[cur ^ 1], z, L.runs, SENT);  // advance only; acc stays 0
+                    }
+                }
                 u -= bprev * vprev;
                 bstore(tv[z], slr, voff, sz);
                 wv[z] = u;
@@ -670,7 +695,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
             const double alpha = uniform(da);
 
             // w -= alpha v;  beta = |w|;  projector dots of w
-            chains_start(L, tid, active, ca, cb);
+            chains_start(L, tid, active, ch);
             double db = 0.0;
 #pragma unroll
             for (int z = 0; z < C; ++z) {
@@ -679,13 +704,13 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
                 wv[z] = w;
                 db += w * w;
                 pin(db);
-                ca.acc += ca.value(pvr, z) * w;
-                pin(ca.acc);
-                ca.finish(L.s[cur ^ 1], z, L.runs, SENT);
-                if (has_b) {
-                    cb.acc += cb.value(pvr, z) * w;
-                    pin(cb.acc);
-                    cb.finish(L.s[cur ^ 1], z, L.runs, SENT);
+#pragma unroll
+                for (int ci = 0; ci < NCH; ++ci) {
+                    if (ci == 0 || ci < nch) {
+                        ch[ci].acc += ch[ci].value(pvr, z) * w;
+                        pin(ch[ci].acc);
+                        ch[ci].finish(L.s[cur ^ 1], z, L.runs, SENT);
+                    }
                 }
             }
             __syncthreads();
@@ -899,22 +924,29 @@ __global__ void sum_partials(const double *partials, int nblk, int width, double
 // Per-cube entry points of this translation unit (SQ_CUBES lists its cubes).
 #define X(c)                                                                                        \
     hipError_t lanczos_c##c(const RecurrenceArgs &a, int nwg, hipStream_t s) {                      \
-        hipLaunchKernelGGL(lanczos_kernel<c>, dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);           \
+        if (a.nch > 2) hipLaunchKernelGGL((lanczos_kernel<c, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
+        else hipLaunchKernelGGL((lanczos_kernel<c, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);       \
         return hipGetLastError();                                                                   \
     }                                                                                               \
     hipError_t moments_c##c(const RecurrenceArgs &a, bool mixed, int nwg, hipStream_t s) {          \
-        if (mixed)                                                                                  \
-            hipLaunchKernelGGL((moments_kernel<c, float>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
-        else                                                                                        \
-            hipLaunchKernelGGL((moments_kernel<c, double>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
+        if (a.nch > 2) {                                                                            \
+            if (mixed) hipLaunchKernelGGL((moments_kernel<c, float, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
+            else hipLaunchKernelGGL((moments_kernel<c, double, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
+        } else {                                                                                    \
+            if (mixed) hipLaunchKernelGGL((moments_kernel<c, float, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
+            else hipLaunchKernelGGL((moments_kernel<c, double, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
+        }                                                                                           \
         return hipGetLastError();                                                                   \
     }                                                                                               \
-    hipError_t occupancy_c##c(bool lanczos, bool mixed, int *nb) {                                  \
+    hipError_t occupancy_c##c(bool lanczos, bool mixed, int nch, int *nb) {                         \
         if (lanczos)                                                                                \
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c>, Shape<c>::BLOCK, 0); \
+            return nch > 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, 4>, Shape<c>::BLOCK, 0) \
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, 2>, Shape<c>::BLOCK, 0); \
         if (mixed)                                                                                  \
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float>, Shape<c>::BLOCK, 0); \
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double>, Shape<c>::BLOCK, 0); \
+            return nch > 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float, 4>, Shape<c>::BLOCK, 0) \
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float, 2>, Shape<c>::BLOCK, 0); \
+        return nch > 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double, 4>, Shape<c>::BLOCK, 0) \
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double, 2>, Shape<c>::BLOCK, 0); \
     }                                                                                               \
     int block_c##c() { return Shape<c>::BLOCK; }
 #ifdef SQ_CUBES
@@ -929,7 +961,7 @@ SQ_ALL_CUBES
 #define X(c)                                                                         \
     hipError_t lanczos_c##c(const RecurrenceArgs &a, int nwg, hipStream_t s);       \
     hipError_t moments_c##c(const RecurrenceArgs &a, bool mixed, int nwg, hipStream_t s); \
-    hipError_t occupancy_c##c(bool lanczos, bool mixed, int *nb);                   \
+    hipError_t occupancy_c##c(bool lanczos, bool mixed, int nch, int *nb);          \
     int block_c##c();
 SQ_ALL_CUBES
 #undef X
@@ -943,9 +975,9 @@ int recurrence_block(int C) {
     }
 }
 
-hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int *blocks_per_cu) {
+hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int nch, int *blocks_per_cu) {
     switch (C) {
-#define X(c) case c: return occupancy_c##c(lanczos, mixed, blocks_per_cu);
+#define X(c) case c: return occupancy_c##c(lanczos, mixed, nch, blocks_per_cu);
         SQ_ALL_CUBES
 #undef X
         default: return hipErrorInvalidValue;
