@@ -35,7 +35,8 @@ def kernel_hash() -> str:
 
 def workload(name):
     from paper_1708_07913_amd import workloads as W
-    return {"paper": W.paper_size_cell, "large": W.large_cell, "tiny": W.tiny_cell}[name]()
+    return {"paper": W.paper_size_cell, "paper-small": W.paper_cell_small, "large": W.large_cell,
+            "tiny": W.tiny_cell}[name]()
 
 
 def traffic_from_profiles(kernel_key: str, workload_name: str):
@@ -113,7 +114,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="paper", choices=["paper", "large", "tiny"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "paper-small", "large", "tiny"])
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()

@@ -30,17 +30,26 @@ namespace {
 
 constexpr int NO = kNoMax;
 
+// Rows of the cube owned by one thread: two y-adjacent columns for the large
+// regions (512-thread workgroups, 256 VGPRs per lane; the pair shares its
+// y-neighbour reads), one column for small regions.
+constexpr int rows_per_thread(int C) { return C >= 19 ? 2 : 1; }
+
 template <int C>
 struct Shape {
+    static constexpr int RB = rows_per_thread(C);
     static constexpr int CC = C * C;
-    static constexpr int P = C + 2 * NO;              // padded plane edge (zero halo of NO)
-    static constexpr int ROWS = P + 2 * NO + 1;       // + an all-zero neighbourhood for idle threads
-    static constexpr int PLANE = ROWS * P + 1;        // + one write-only cell for idle threads
-    static constexpr int IDLE_READ = (P + NO) * P + NO;
+    static constexpr int YP = (C + RB - 1) / RB;            // row groups
+    static constexpr int NT = C * YP;                        // threads owning columns
+    static constexpr int P = C + 2 * NO;                     // padded plane edge (zero halo NO)
+    static constexpr int ROWS = P + 2 * NO + RB;             // + an all-zero neighbourhood for idle threads
+    static constexpr int PLANE = ROWS * P + 1;               // + one write-only cell for idle threads
+    static constexpr int IDLE_CORNER = P * P;
     static constexpr int IDLE_WRITE = ROWS * P;
-    static constexpr int BLOCK = (CC + 63) / 64 * 64;
+    static constexpr int BLOCK = (NT + 63) / 64 * 64;
     static constexpr int NW = BLOCK / 64;
     static constexpr int MAXRUNS = 6 * CC + 512;
+    static constexpr int CPT = (CC + BLOCK - 1) / BLOCK;     // columns per thread in the set-up scan
 };
 
 // Run record: x = image slot | z_first << 8 | z_last << 16 | chain << 24,
@@ -89,7 +98,7 @@ __device__ __forceinline__ int pmod(int a, int n) {
 
 // Raw buffer access: SGPR descriptor + one VGPR byte offset + SGPR byte offset,
 // so that per-plane addresses stay scalar.  Out-of-range offsets read 0 and
-// drop stores (used for idle threads).
+// drop stores (used for idle columns).
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, long long bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
@@ -148,8 +157,8 @@ __device__ __forceinline__ void block_sum2(Lds<C, T, NCH> &L, double &a, double 
         L.bc[tid] = s;
     }
     __syncthreads();
-    a = L.bc[0];
-    b = L.bc[1];
+    a = uniform(L.bc[0]);
+    b = uniform(L.bc[1]);
     __syncthreads();
 }
 
@@ -182,8 +191,8 @@ __device__ void sort_runs(uint2 *runs, int b, int e, bool with_chain) {
 
 // ---------------------------------------------------------------------------
 // Region of influence of node q: projector images meeting the cube and, per
-// cube column, the clipped z-runs of their spheres split into two chains of
-// non-overlapping runs (a second chain exists only where two spheres overlap).
+// cube column, the clipped z-runs of their spheres split into chains of
+// disjoint runs (more than one chain only where spheres overlap).
 // ---------------------------------------------------------------------------
 template <int C, typename T, int NCH>
 __device__ void setup_region(const RecurrenceArgs &A, Lds<C, T, NCH> &L, int qi, int qj, int qk, int tid) {
@@ -264,10 +273,14 @@ __device__ void setup_region(const RecurrenceArgs &A, Lds<C, T, NCH> &L, int qi,
         }
         __syncthreads();
         if (pass == 0) {
-            // exclusive scan of the per-column counts
-            int v = 0;
-            if (tid < S::CC) v = L.col_fill[tid];
-            int incl = v;
+            // exclusive scan of the per-column counts: each thread sums a chunk
+            // of CPT columns, then a wave/workgroup scan of the chunk sums
+            const int c0 = tid * S::CPT;
+            int chunk = 0;
+#pragma unroll
+            for (int i = 0; i < S::CPT; ++i)
+                if (c0 + i < S::CC) chunk += L.col_fill[c0 + i];
+            int incl = chunk;
             const int lane = tid & 63;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
@@ -278,26 +291,32 @@ __device__ void setup_region(const RecurrenceArgs &A, Lds<C, T, NCH> &L, int qi,
             __syncthreads();
             int base = 0;
             for (int w = 0; w < (tid >> 6); ++w) base += L.scan_tot[w];
-            if (tid < S::CC) {
-                L.col_start[tid] = base + incl - v;
-                L.col_fill[tid] = base + incl - v;
-                if (tid == S::CC - 1) {
-                    L.col_start[S::CC] = base + incl;
-                    if (base + incl > S::MAXRUNS) L.bad = 1;
+            int run = base + incl - chunk;
+#pragma unroll
+            for (int i = 0; i < S::CPT; ++i) {
+                if (c0 + i < S::CC) {
+                    const int v = L.col_fill[c0 + i];
+                    L.col_start[c0 + i] = run;
+                    L.col_fill[c0 + i] = run;
+                    run += v;
                 }
+            }
+            if (c0 < S::CC && c0 + S::CPT >= S::CC) {
+                L.col_start[S::CC] = run;
+                if (run > S::MAXRUNS) L.bad = 1;
             }
             __syncthreads();
         }
     }
     if (L.bad) {
         if (tid == 0) atomicOr(A.flags, kFlagRuns);
-        if (tid <= S::CC) L.col_start[tid] = 0;
+        for (int i = tid; i <= S::CC; i += S::BLOCK) L.col_start[i] = 0;
         __syncthreads();
     }
     // per column: sort by z_first, split first-fit into chains of disjoint runs
     // (as many as spheres overlap at one point), chain 0 first
-    if (tid < S::CC) {
-        const int b = L.col_start[tid], e = L.col_start[tid + 1];
+    for (int col = tid; col < S::CC; col += S::BLOCK) {
+        const int b = L.col_start[col], e = L.col_start[col + 1];
         sort_runs(L.runs, b, e, false);
         int last[NCH], cnt[NCH];
 #pragma unroll
@@ -334,7 +353,7 @@ __device__ void setup_region(const RecurrenceArgs &A, Lds<C, T, NCH> &L, int qi,
         int off = 0;
 #pragma unroll
         for (int ci = 0; ci < NCH; ++ci) {
-            L.col_off[tid][ci] = off;
+            L.col_off[col][ci] = off;
             off += cnt[ci];
         }
     }
@@ -344,15 +363,17 @@ __device__ void setup_region(const RecurrenceArgs &A, Lds<C, T, NCH> &L, int qi,
 // One chain of disjoint z-runs of a column, walked plane by plane without
 // branches except at the end of a run.
 struct Chain {
-    int i, e;
-    int z0, z1, vb, sl;
+    int i, e;       // current record, end of the chain
+    unsigned rx;    // slot | z_first << 8 | z_last << 16 of the current record
+    int vb;         // value base of the current record
     double acc;
 
+    __device__ __forceinline__ int sl() const { return (int)(rx & 0xFFu); }
+    __device__ __forceinline__ int z0() const { return (int)((rx >> 8) & 0xFFu); }
+    __device__ __forceinline__ int z1() const { return (int)((rx >> 16) & 0xFFu); }
     __device__ __forceinline__ void load(const uint2 *runs, int sentinel) {
         const uint2 r = runs[i < e ? i : sentinel];
-        sl = (int)(r.x & 0xFFu);
-        z0 = (int)((r.x >> 8) & 0xFFu);
-        z1 = (int)((r.x >> 16) & 0xFFu);
+        rx = r.x;
         vb = (int)r.y;
     }
     __device__ __forceinline__ void start(const uint2 *runs, int b, int end, int sentinel) {
@@ -363,13 +384,13 @@ struct Chain {
     }
     // projector value at plane z (0 outside the current run)
     __device__ __forceinline__ double value(__amdgpu_buffer_rsrc_t pv, int z) const {
-        const bool act = (z >= z0) & (z <= z1);
+        const bool act = (z >= z0()) & (z <= z1());
         return bload<double>(pv, act ? (unsigned)(vb + z) * 8u : kIdleOffset, 0u);
     }
     // after plane z: a finished run adds its dot product into s[slot]
     __device__ __forceinline__ void finish(double *s, int z, const uint2 *runs, int sentinel) {
-        if (z == z1) {
-            atomicAdd(&s[sl], acc);
+        if (z == z1()) {
+            atomicAdd(&s[sl()], acc);
             acc = 0.0;
             ++i;
             load(runs, sentinel);
@@ -377,15 +398,40 @@ struct Chain {
     }
 };
 
+// Columns owned by one thread and their per-column addressing.
+template <int C>
+struct Cols {
+    using S = Shape<C>;
+    static constexpr int RB = S::RB;
+    int x, y0;
+    int corner;                 // LDS offset of the thread's neighbourhood corner
+    int col[RB];                // cube column index, or -1
+    int pcw[RB];                // LDS write offset of the column's plane value
+    __device__ __forceinline__ void init(int tid) {
+        const bool t_active = tid < S::NT;
+        x = t_active ? tid % C : 0;
+        y0 = t_active ? (tid / C) * RB : 0;
+        corner = t_active ? y0 * S::P + x : S::IDLE_CORNER;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const bool ok = t_active && (y0 + r < C);
+            col[r] = ok ? (y0 + r) * C + x : -1;
+            pcw[r] = ok ? corner + (NO + r) * S::P + NO : S::IDLE_WRITE;
+        }
+    }
+    __device__ __forceinline__ bool valid(int r) const { return col[r] >= 0; }
+};
+
 template <int C, typename T, int NCH>
-__device__ __forceinline__ void chains_start(const Lds<C, T, NCH> &L, int tid, bool active, Chain (&ch)[NCH]) {
+__device__ __forceinline__ void chains_start(const Lds<C, T, NCH> &L, int column, Chain (&ch)[NCH]) {
     constexpr int SENT = Shape<C>::MAXRUNS;
-    const int b = active ? L.col_start[tid] : 0;
-    const int e = active ? L.col_start[tid + 1] : 0;
+    const bool ok = column >= 0;
+    const int b = ok ? L.col_start[column] : 0;
+    const int e = ok ? L.col_start[column + 1] : 0;
 #pragma unroll
     for (int ci = 0; ci < NCH; ++ci) {
-        const int s0 = b + (active ? L.col_off[tid][ci] : 0);
-        const int s1 = ci + 1 < NCH ? b + (active ? L.col_off[tid][ci + 1] : 0) : e;
+        const int s0 = b + (ok ? L.col_off[column][ci] : 0);
+        const int s1 = ci + 1 < NCH ? b + (ok ? L.col_off[column][ci + 1] : 0) : e;
         ch[ci].start(L.runs, s0, s1, SENT);
     }
 }
@@ -396,26 +442,65 @@ __device__ __forceinline__ void node_coords(long long q, int n, int &qi, int &qj
     qk = (int)(q / ((long long)n * n));
 }
 
-// Projector dots of the register column tv: s[dst][I] += p_I . tv
+// Projector dots of the register columns tv: s[dst][I] += p_I . tv
 template <int C, typename T, int NCH, typename V>
-__device__ __forceinline__ void projector_dots(Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr, const V (&tv)[C],
-                                               int dst, int tid, bool active, int nch) {
+__device__ __forceinline__ void projector_dots(Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr,
+                                               const V (&tv)[Shape<C>::RB][C], const Cols<C> &cl, int dst,
+                                               int nch) {
     constexpr int SENT = Shape<C>::MAXRUNS;
-    Chain ch[NCH];
-    chains_start(L, tid, active, ch);
+    constexpr int RB = Shape<C>::RB;
+    Chain ch[RB][NCH];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) chains_start(L, cl.col[r], ch[r]);
 #pragma unroll
     for (int z = 0; z < C; ++z) {
-        const double t = (double)tv[z];
 #pragma unroll
-        for (int ci = 0; ci < NCH; ++ci) {
-            if (ci == 0 || ci < nch) {
-                ch[ci].acc += ch[ci].value(pvr, z) * t;
-                pin(ch[ci].acc);
-                ch[ci].finish(L.s[dst], z, L.runs, SENT);
+        for (int r = 0; r < RB; ++r) {
+            const double t = (double)tv[r][z];
+#pragma unroll
+            for (int ci = 0; ci < NCH; ++ci) {
+                if (ci == 0 || ci < nch) {
+                    ch[r][ci].acc += ch[r][ci].value(pvr, z) * t;
+                    pin(ch[r][ci].acc);
+                    ch[r][ci].finish(L.s[dst], z, L.runs, SENT);
+                }
             }
         }
     }
     __syncthreads();
+}
+
+// Stencil part of (H t)[column r, plane z] from the LDS plane (x and y legs)
+// and the register column (z legs): sum_d kw[d] (x pair + y pair + z pair).
+// `yrow` holds the plane values of rows y0 - NO .. y0 + RB - 1 + NO at x.
+template <int C, typename T>
+__device__ __forceinline__ double stencil_sum(const T *pl, const T (&yrow)[2 * NO + Shape<C>::RB],
+                                              const T (&tv)[C], int r, int z, const double (&kw)[NO + 1]) {
+    constexpr int P = Shape<C>::P;
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 1; d <= NO; ++d) {
+        const T xs = pl[(NO + r) * P + NO + d] + pl[(NO + r) * P + NO - d];
+        const T ys = yrow[NO + r + d] + yrow[NO + r - d];
+        T zs = T(0);
+        if (z + d < C) zs = tv[z + d];
+        if (z - d >= 0) zs = zs + tv[z - d];
+        acc += kw[d] * ((double)xs + (double)ys + (double)zs);
+    }
+    return acc;
+}
+
+// Rows of the y legs for all RB columns of the thread: LDS for the other
+// rows, registers for the thread's own rows.
+template <int C, typename T>
+__device__ __forceinline__ void load_yrows(const T *pl, const T (&tv)[Shape<C>::RB][C], int z,
+                                           T (&yrow)[2 * NO + Shape<C>::RB]) {
+    constexpr int P = Shape<C>::P, RB = Shape<C>::RB;
+#pragma unroll
+    for (int j = 0; j < 2 * NO + RB; ++j) {
+        if (j >= NO && j < NO + RB) yrow[j] = tv[j - NO][z];
+        else yrow[j] = pl[j * P + NO];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -427,24 +512,26 @@ __device__ __forceinline__ void projector_dots(Lds<C, T, NCH> &L, __amdgpu_buffe
 template <int C, typename T, int NCH>
 __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs A) {
     using S = Shape<C>;
+    constexpr int RB = S::RB;
     constexpr int MC = (C - 1) / 2;
     constexpr int SENT = S::MAXRUNS;
     __shared__ Lds<C, T, NCH> L;
     const int tid = threadIdx.x;
-    const bool active = tid < S::CC;
-    const int x = active ? tid % C : 0, y = active ? tid / C : 0;
-    // neighbourhood corner: every stencil read is corner + a positive immediate
-    const int pcr = active ? (y + NO) * S::P + (x + NO) : S::IDLE_READ;
-    const int corner = pcr - NO * S::P - NO;
-    const int pcw = active ? pcr : S::IDLE_WRITE;
-    const bool is_centre = (tid == MC * C + MC);
+    Cols<C> cl;
+    cl.init(tid);
+    int centre_r = -1;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (cl.col[r] == MC * C + MC) centre_r = r;
     const int n = A.n;
     const int npl = A.npl, half = npl / 2;
     const __amdgpu_buffer_rsrc_t slr =
         make_rsrc(reinterpret_cast<T *>(A.slots) + (long long)blockIdx.x * A.slot_elems, A.slot_elems * (long long)sizeof(T));
     const __amdgpu_buffer_rsrc_t vr = sizeof(T) == 4 ? make_rsrc(A.veff32, A.nd * 4) : make_rsrc(A.veff, A.nd * 8);
     const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
-    const unsigned voff = active ? (unsigned)tid * (unsigned)sizeof(T) : kIdleOffset;
+    unsigned voff[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * (unsigned)sizeof(T) : kIdleOffset;
     const int nwg = gridDim.x, xcd = blockIdx.x & 7, per = nwg >> 3, lw = blockIdx.x >> 3;
     const long long qlo = A.nd * xcd / 8, qhi = A.nd * (xcd + 1) / 8;
     const double kin0 = -3.0 * A.w[0];
@@ -459,85 +546,96 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
         const double chi = uniform(A.chi[q]), zeta = uniform(A.zeta[q]);
         const double invz = uniform(1.0 / zeta);
         double kw[NO + 1];
+        kw[0] = 0.0;
 #pragma unroll
         for (int d = 1; d <= NO; ++d) kw[d] = uniform(-0.5 * A.w[d] * invz);
         const double c0 = uniform(kin0 - chi);
-        const unsigned vcol =
-            active ? (unsigned)(pmod(qi - A.m + x, n) + n * pmod(qj - A.m + y, n)) * (unsigned)sizeof(T) : kIdleOffset;
+        unsigned vcol[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            vcol[r] = cl.valid(r) ? (unsigned)(pmod(qi - A.m + cl.x, n) + n * pmod(qj - A.m + cl.y0 + r, n)) *
+                                        (unsigned)sizeof(T)
+                                  : kIdleOffset;
         double *mrow = A.moments + q * (long long)(npl + 1);
 
-        T tv[C];
+        T tv[RB][C];
 #pragma unroll
-        for (int z = 0; z < C; ++z) tv[z] = T((is_centre && z == MC) ? 1 : 0);
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int z = 0; z < C; ++z) tv[r][z] = T((centre_r == r && z == MC) ? 1 : 0);
         if (tid == 0) mrow[0] = 1.0;
         int cur = 0;
-        projector_dots(L, pvr, tv, cur, tid, active, nch);
+        projector_dots(L, pvr, tv, cl, cur, nch);
 
         for (int k = 0; k < half; ++k) {
             const double al = k == 0 ? 1.0 : 2.0;
             const double scale = uniform(al * invz);
             for (int i = tid; i < kMaxImages; i += S::BLOCK)
                 L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur][i] : 0.0;
-            Chain ch[NCH];
-            chains_start(L, tid, active, ch);
+            Chain ch[RB][NCH];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) chains_start(L, cl.col[r], ch[r]);
             double *snext = L.s[cur ^ 1];
             double d1 = 0.0, d2 = 0.0;
             unsigned zb = zbase;
             asm volatile("" : "+s"(zb));  // keep the per-plane offsets inside the step loop
-            T nv[C];
+            T nv[RB][C];
 #pragma unroll
             for (int z = 0; z < C; ++z) {
                 const unsigned sz = (unsigned)(z * S::CC) * (unsigned)sizeof(T);
                 const unsigned vz_off = (unsigned)(n * n) * ((zb + (unsigned)z) % (unsigned)n) * (unsigned)sizeof(T);
-                const double vz = (double)bload<T>(vr, vcol, vz_off);
-                double tprev = 0.0;
-                if (k > 0) tprev = (double)bload<T>(slr, voff, sz);
-                L.plane[z & 1][pcw] = tv[z];
+                double vz[RB], tprev[RB];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    vz[r] = (double)bload<T>(vr, vcol[r], vz_off);
+                    tprev[r] = 0.0;
+                    if (k > 0) tprev[r] = (double)bload<T>(slr, voff[r], sz);
+                    L.plane[z & 1][cl.pcw[r]] = tv[r][z];
+                }
                 __syncthreads();
-                const T *pl = L.plane[z & 1] + corner;
-                constexpr int PC = NO * S::P + NO;
-                double acc = 0.0;
+                const T *pl = L.plane[z & 1] + cl.corner;
+                T yrow[2 * NO + RB];
+                load_yrows<C, T>(pl, tv, z, yrow);
 #pragma unroll
-                for (int d = 1; d <= NO; ++d) {
-                    const T xs = pl[PC + d] + pl[PC - d];
-                    const T ys = pl[PC + d * S::P] + pl[PC - d * S::P];
-                    T zs = T(0);
-                    if (z + d < C) zs = tv[z + d];
-                    if (z - d >= 0) zs = zs + tv[z - d];
-                    acc += kw[d] * ((double)xs + (double)ys + (double)zs);
-                }
-                const double tz = (double)tv[z];
-                const double u = acc + (vz + c0) * invz * tz;
-                double pv[NCH];
-                double nvd = al * u - tprev;
+                for (int r = 0; r < RB; ++r) {
+                    const double acc = stencil_sum<C, T>(pl, yrow, tv[r], r, z, kw);
+                    const double tz = (double)tv[r][z];
+                    const double u = acc + (vz[r] + c0) * invz * tz;
+                    double pv[NCH];
+                    double nvd = al * u - tprev[r];
 #pragma unroll
-                for (int ci = 0; ci < NCH; ++ci) {
-                    pv[ci] = 0.0;
-                    if (ci == 0 || ci < nch) {
-                        pv[ci] = ch[ci].value(pvr, z);
-                        nvd += L.cs[ch[ci].sl] * pv[ci];
+                    for (int ci = 0; ci < NCH; ++ci) {
+                        pv[ci] = 0.0;
+                        if (ci == 0 || ci < nch) {
+                            pv[ci] = ch[r][ci].value(pvr, z);
+                            nvd += L.cs[ch[r][ci].sl()] * pv[ci];
+                        }
                     }
-                }
-                const T nvt = T(nvd);
-                nvd = (double)nvt;
-                nv[z] = nvt;
-                bstore(tv[z], slr, voff, sz);
-                d1 += nvd * nvd;
-                d2 += nvd * tz;
-                pin(d1);
-                pin(d2);
+                    // a column past the cube edge (odd C) shares its neighbour reads
+                    // with a real column; it must stay zero, since it is that
+                    // column's y + 1 neighbour
+                    if (!cl.valid(r)) nvd = 0.0;
+                    const T nvt = T(nvd);
+                    nvd = (double)nvt;
+                    nv[r][z] = nvt;
+                    bstore(tv[r][z], slr, voff[r], sz);
+                    d1 += nvd * nvd;
+                    d2 += nvd * tz;
+                    pin(d1);
+                    pin(d2);
 #pragma unroll
-                for (int ci = 0; ci < NCH; ++ci) {
-                    if (ci == 0 || ci < nch) {
-                        ch[ci].acc += pv[ci] * nvd;
-                        pin(ch[ci].acc);
-                        ch[ci].finish(snext, z, L.runs, SENT);
+                    for (int ci = 0; ci < NCH; ++ci) {
+                        if (ci == 0 || ci < nch) {
+                            ch[r][ci].acc += pv[ci] * nvd;
+                            pin(ch[r][ci].acc);
+                            ch[r][ci].finish(snext, z, L.runs, SENT);
+                        }
                     }
-                }
-                if (z == MC && is_centre) {
-                    mrow[k + 1] = nvd;
-                    if (k == 0) L.bc[2] = nvd;
-                    if (fabs(nvd) > 1.0 + A.bounds_tol) atomicOr(A.flags, kFlagBounds);
+                    if (z == MC && centre_r == r) {
+                        mrow[k + 1] = nvd;
+                        if (k == 0) L.bc[2] = nvd;
+                        if (fabs(nvd) > 1.0 + A.bounds_tol) atomicOr(A.flags, kFlagBounds);
+                    }
                 }
             }
             __syncthreads();
@@ -554,7 +652,9 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
                 }
             }
 #pragma unroll
-            for (int z = 0; z < C; ++z) tv[z] = nv[z];
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int z = 0; z < C; ++z) tv[r][z] = nv[r][z];
             for (int i = tid; i < kMaxImages; i += S::BLOCK) L.s[cur][i] = 0.0;
             cur ^= 1;
             __syncthreads();
@@ -602,29 +702,31 @@ template <int C, int NCH>
 __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs A) {
     using S = Shape<C>;
     using T = double;
+    constexpr int RB = S::RB;
     constexpr int SENT = S::MAXRUNS;
     __shared__ Lds<C, T, NCH> L;
     __shared__ LanczosLds LL;
     const int tid = threadIdx.x;
-    const bool active = tid < S::CC;
-    const int x = active ? tid % C : 0, y = active ? tid / C : 0;
-    const int pcr = active ? (y + NO) * S::P + (x + NO) : S::IDLE_READ;
-    const int corner = pcr - NO * S::P - NO;
-    const int pcw = active ? pcr : S::IDLE_WRITE;
+    Cols<C> cl;
+    cl.init(tid);
     const int n = A.n;
     const __amdgpu_buffer_rsrc_t slr =
         make_rsrc(reinterpret_cast<T *>(A.slots) + (long long)blockIdx.x * A.slot_elems, A.slot_elems * 8);
     const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
     const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
-    const unsigned voff = active ? (unsigned)tid * 8u : kIdleOffset;
+    unsigned voff[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * 8u : kIdleOffset;
     const int nwg = gridDim.x, xcd = blockIdx.x & 7, per = nwg >> 3, lw = blockIdx.x >> 3;
     const long long qlo = A.nd * xcd / 8, qhi = A.nd * (xcd + 1) / 8;
     const double kin0 = -3.0 * A.w[0];
     double kw[NO + 1];
+    kw[0] = 0.0;
 #pragma unroll
     for (int d = 1; d <= NO; ++d) kw[d] = -0.5 * A.w[d];
     const long long ns = (long long)C * C * C;
     const int kmax = (long long)A.n_lanczos < ns ? A.n_lanczos : (int)ns;
+    const double rnorm = 1.0 / A.start_norm;
 
     for (long long q = qlo + lw; q < qhi; q += per) {
         int qi, qj, qk;
@@ -633,14 +735,21 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
         const int ni = L.ni < kMaxImages ? L.ni : kMaxImages;
         const int nch = L.nch;
         const unsigned zbase = (unsigned)pmod(qk - A.m, n);
-        const unsigned vcol = active ? (unsigned)(pmod(qi - A.m + x, n) + n * pmod(qj - A.m + y, n)) * 8u : kIdleOffset;
-
-        double tv[C];
+        unsigned vcol[RB];
 #pragma unroll
-        for (int z = 0; z < C; ++z)
-            tv[z] = active ? (unit_from_seed((unsigned long long)(x + C * (y + C * z))) - 0.5) / A.start_norm : 0.0;
+        for (int r = 0; r < RB; ++r)
+            vcol[r] = cl.valid(r) ? (unsigned)(pmod(qi - A.m + cl.x, n) + n * pmod(qj - A.m + cl.y0 + r, n)) * 8u
+                                  : kIdleOffset;
+
+        double tv[RB][C];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int z = 0; z < C; ++z)
+                tv[r][z] = cl.valid(r) ? (unit_from_seed((unsigned long long)(cl.col[r] + C * C * z)) - 0.5) * rnorm
+                                       : 0.0;
         int cur = 0;
-        projector_dots(L, pvr, tv, cur, tid, active, nch);
+        projector_dots(L, pvr, tv, cl, cur, nch);
 
         double bprev = 0.0, gersh = 0.0;
         int ksteps = kmax;
@@ -648,68 +757,72 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
             // w = H v - beta_{j-1} v_{j-1};  slot <- v;  alpha = w . v
             for (int i = tid; i < kMaxImages; i += S::BLOCK)
                 L.cs[i] = i < ni ? L.img_coef[i] * L.s[cur][i] : 0.0;
-            Chain ch[NCH];
-            chains_start(L, tid, active, ch);
+            Chain ch[RB][NCH];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) chains_start(L, cl.col[r], ch[r]);
             unsigned zb = zbase;
             asm volatile("" : "+s"(zb));
-            double wv[C];
+            double wv[RB][C];
             double da = 0.0;
 #pragma unroll
             for (int z = 0; z < C; ++z) {
                 const unsigned sz = (unsigned)(z * S::CC) * 8u;
                 const unsigned vz_off = (unsigned)(n * n) * ((zb + (unsigned)z) % (unsigned)n) * 8u;
-                const double vz = bload<double>(vr, vcol, vz_off);
-                double vprev = 0.0;
-                if (j > 0) vprev = bload<double>(slr, voff, sz);
-                L.plane[z & 1][pcw] = tv[z];
+                double vz[RB], vprev[RB];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    vz[r] = bload<double>(vr, vcol[r], vz_off);
+                    vprev[r] = 0.0;
+                    if (j > 0) vprev[r] = bload<double>(slr, voff[r], sz);
+                    L.plane[z & 1][cl.pcw[r]] = tv[r][z];
+                }
                 __syncthreads();
-                const double *pl = L.plane[z & 1] + corner;
-                constexpr int PC = NO * S::P + NO;
-                double acc = 0.0;
+                const double *pl = L.plane[z & 1] + cl.corner;
+                double yrow[2 * NO + RB];
+                load_yrows<C, double>(pl, tv, z, yrow);
 #pragma unroll
-                for (int d = 1; d <= NO; ++d) {
-                    const double xs = pl[PC + d] + pl[PC - d];
-                    const double ys = pl[PC + d * S::P] + pl[PC - d * S::P];
-                    double zs = 0.0;
-                    if (z + d < C) zs = tv[z + d];
-                    if (z - d >= 0) zs = zs + tv[z - d];
-                    acc += kw[d] * (xs + ys + zs);
-                }
-                double u = acc + (vz + kin0) * tv[z];
+                for (int r = 0; r < RB; ++r) {
+                    double u = stencil_sum<C, double>(pl, yrow, tv[r], r, z, kw) + (vz[r] + kin0) * tv[r][z];
 #pragma unroll
-                for (int ci = 0; ci < NCH; ++ci) {
-                    if (ci == 0 || ci < nch) {
-                        u += L.cs[ch[ci].sl] * ch[ci].value(pvr, z);
-                        ch[ci].finish(L.s[cur ^ 1], z, L.runs, SENT);  // advance only; acc stays 0
+                    for (int ci = 0; ci < NCH; ++ci) {
+                        if (ci == 0 || ci < nch) {
+                            u += L.cs[ch[r][ci].sl()] * ch[r][ci].value(pvr, z);
+                            ch[r][ci].finish(L.s[cur ^ 1], z, L.runs, SENT);  // advance only; acc stays 0
+                        }
                     }
+                    u -= bprev * vprev[r];
+                    if (!cl.valid(r)) u = 0.0;  // column past the cube edge stays zero
+                    bstore(tv[r][z], slr, voff[r], sz);
+                    wv[r][z] = u;
+                    da += u * tv[r][z];
+                    pin(da);
                 }
-                u -= bprev * vprev;
-                bstore(tv[z], slr, voff, sz);
-                wv[z] = u;
-                da += u * tv[z];
-                pin(da);
             }
             __syncthreads();
             double dummy = 0.0;
             block_sum2(L, da, dummy, tid);
-            const double alpha = uniform(da);
+            const double alpha = da;
 
             // w -= alpha v;  beta = |w|;  projector dots of w
-            chains_start(L, tid, active, ch);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) chains_start(L, cl.col[r], ch[r]);
             double db = 0.0;
 #pragma unroll
             for (int z = 0; z < C; ++z) {
-                const double v = bload<double>(slr, voff, (unsigned)(z * S::CC) * 8u);
-                const double w = wv[z] - alpha * v;
-                wv[z] = w;
-                db += w * w;
-                pin(db);
 #pragma unroll
-                for (int ci = 0; ci < NCH; ++ci) {
-                    if (ci == 0 || ci < nch) {
-                        ch[ci].acc += ch[ci].value(pvr, z) * w;
-                        pin(ch[ci].acc);
-                        ch[ci].finish(L.s[cur ^ 1], z, L.runs, SENT);
+                for (int r = 0; r < RB; ++r) {
+                    const double v = bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u);
+                    const double w = wv[r][z] - alpha * v;
+                    wv[r][z] = w;
+                    db += w * w;
+                    pin(db);
+#pragma unroll
+                    for (int ci = 0; ci < NCH; ++ci) {
+                        if (ci == 0 || ci < nch) {
+                            ch[r][ci].acc += ch[r][ci].value(pvr, z) * w;
+                            pin(ch[r][ci].acc);
+                            ch[r][ci].finish(L.s[cur ^ 1], z, L.runs, SENT);
+                        }
                     }
                 }
             }
@@ -726,10 +839,13 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
                 ksteps = j + 1;
                 break;
             }
+            const double rb = uniform(1.0 / beta);
 #pragma unroll
-            for (int z = 0; z < C; ++z) tv[z] = wv[z] / beta;
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int z = 0; z < C; ++z) tv[r][z] = wv[r][z] * rb;
             for (int i = tid; i < kMaxImages; i += S::BLOCK) {
-                L.s[cur ^ 1][i] = L.s[cur ^ 1][i] / beta;
+                L.s[cur ^ 1][i] = L.s[cur ^ 1][i] * rb;
                 L.s[cur][i] = 0.0;
             }
             cur ^= 1;

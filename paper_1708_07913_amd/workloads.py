@@ -164,6 +164,11 @@ def paper_size_cell() -> Workload:
     return fcc_workload("al256_h0.4_rc6", 4, 7.78, 0.15, 2, 0.4, 6.0, 48, 1.0)
 
 
+def paper_cell_small() -> Workload:
+    """2x2x2 FCC version of the paper-size cell (32 atoms, 39^3 grid, same 31^3 regions)."""
+    return fcc_workload("al32_h0.4_rc6", 2, 7.78, 0.15, 2, 0.4, 6.0, 48, 1.0)
+
+
 def large_cell(precision: str = "fp64") -> Workload:
     """7x7x7 FCC (1372 atoms, 54.46 Bohr), h 0.5 (109^3), R_cut 7 (29^3), n_pl 64."""
     return fcc_workload("al1372_h0.5_rc7", 7, 7.78, 0.2, 5, 0.5, 7.0, 64, 1.0,

@@ -87,6 +87,10 @@ EDGE_CASES = {
     "one_atom_fd8_cube15": (1, 10.0, 0.3, 3, 0.5, 3.5, 16, 3.0, 8, 1),
     "ragged_n13_cube11": (1, 6.5, 0.1, 9, 0.5, 2.5, 20, 1.0, 12, None),
     "npl4": (1, 8.0, 0.1, 2, 0.5, 1.0, 4, 5.0, 12, None),
+    # two cube columns per thread, odd C: the last thread's second column lies
+    # past the cube edge and must stay zero
+    "cube19_two_columns": (1, 8.0, 0.1, 1, 0.5, 4.5, 24, 1.0, 12, None),
+    "cube21_two_columns": (1, 10.0, 0.2, 4, 0.5, 5.0, 16, 2.0, 12, None),
 }
 
 
