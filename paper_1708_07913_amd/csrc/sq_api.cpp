@@ -64,7 +64,7 @@ struct sq_ctx {
     int max_overlap = 0;
     size_t off_atoms = 0, off_runs = 0, off_pvals = 0, off_chi = 0, off_zeta = 0, off_ctab = 0,
            off_rk = 0, off_W = 0, off_part = 0, off_scal = 0, off_flags = 0, off_v32 = 0,
-           off_slots = 0, total = 0;
+           off_slots = 0, off_wslots = 0, total = 0;
     char *ws = nullptr;
     const double *veff = nullptr;
     int state = kSetup;
@@ -197,6 +197,7 @@ sq::RecurrenceArgs recurrence_args(sq_ctx *c) {
     a.zeta = c->at<double>(c->off_zeta);
     a.npl = c->npl;
     a.slots = c->ws + c->off_slots;
+    a.wslots = c->ws + c->off_wslots;
     a.slot_elems = c->ns;
     a.flags = c->at<int>(c->off_flags);
     a.nch = c->nch;
@@ -254,6 +255,7 @@ void layout(sq_ctx *c) {
     c->off_flags = take(64);
     c->off_v32 = take(c->opt.precision == SQ_FP32_MIXED ? size_t(c->nd) * sizeof(float) : 0);
     c->off_slots = take(size_t(c->nwg_slots) * size_t(c->ns) * sizeof(double));
+    c->off_wslots = take(size_t(c->nwg_lanczos) * size_t(c->ns) * sizeof(double));
     c->total = off;
 }
 

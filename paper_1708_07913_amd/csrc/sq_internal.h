@@ -52,6 +52,7 @@ struct RecurrenceArgs {
     double *moments;        // N_d x (npl + 1)
     int npl;
     void *slots;            // nwg slots of C^3 elements
+    void *wslots;           // second set of slots (Lanczos: H v - beta v_prev)
     long long slot_elems;
     int *flags;
     int nch;                // projector chains per column: 2 or 4 (max sphere overlap depth)

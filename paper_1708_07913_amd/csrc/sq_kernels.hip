@@ -470,17 +470,50 @@ __device__ __forceinline__ void projector_dots(Lds<C, T, NCH> &L, __amdgpu_buffe
     __syncthreads();
 }
 
-// Stencil part of (H t)[column r, plane z] from the LDS plane (x and y legs)
-// and the register column (z legs): sum_d kw[d] (x pair + y pair + z pair).
-// `yrow` holds the plane values of rows y0 - NO .. y0 + RB - 1 + NO at x.
+// The LDS plane of one z, seen from a thread's neighbourhood through three
+// base pointers whose stencil offsets all fit the immediate fields of the LDS
+// instructions: the NO rows above the thread's rows, the thread's own rows
+// (x legs), and the NO rows below.  The plane buffer offset is made opaque per
+// plane so that the bases are recomputed (three adds) instead of being kept
+// live for every plane of the unrolled sweep.
 template <int C, typename T>
-__device__ __forceinline__ double stencil_sum(const T *pl, const T (&yrow)[2 * NO + Shape<C>::RB],
+struct PlaneView {
+    const T *ylo, *xr, *yhi;
+    __device__ __forceinline__ PlaneView(const T *plane0, int buf, int corner) {
+        constexpr int P = Shape<C>::P, RB = Shape<C>::RB, PLANE = Shape<C>::PLANE;
+        int boff = buf * PLANE;
+        asm volatile("" : "+s"(boff));
+        const T *pl = plane0 + boff + corner;
+        ylo = pl + NO;
+        xr = pl + NO * P;
+        yhi = pl + (NO + RB) * P + NO;
+    }
+};
+
+// Rows of the y legs for all RB columns of the thread: LDS for the other
+// rows, registers for the thread's own rows.
+template <int C, typename T>
+__device__ __forceinline__ void load_yrows(const PlaneView<C, T> &pv, const T (&tv)[Shape<C>::RB][C], int z,
+                                           T (&yrow)[2 * NO + Shape<C>::RB]) {
+    constexpr int P = Shape<C>::P, RB = Shape<C>::RB;
+#pragma unroll
+    for (int j = 0; j < NO; ++j) yrow[j] = pv.ylo[j * P];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) yrow[NO + r] = tv[r][z];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) yrow[NO + RB + j] = pv.yhi[j * P];
+}
+
+// Stencil part of (H t)[column r, plane z]: sum_d kw[d] (x pair + y pair + z
+// pair), x legs from the LDS plane, y legs from `yrow`, z legs from registers.
+template <int C, typename T>
+__device__ __forceinline__ double stencil_sum(const PlaneView<C, T> &pv, const T (&yrow)[2 * NO + Shape<C>::RB],
                                               const T (&tv)[C], int r, int z, const double (&kw)[NO + 1]) {
     constexpr int P = Shape<C>::P;
     double acc = 0.0;
 #pragma unroll
     for (int d = 1; d <= NO; ++d) {
-        const T xs = pl[(NO + r) * P + NO + d] + pl[(NO + r) * P + NO - d];
+        const T xs = pv.xr[r * P + NO + d] + pv.xr[r * P + NO - d];
         const T ys = yrow[NO + r + d] + yrow[NO + r - d];
         T zs = T(0);
         if (z + d < C) zs = tv[z + d];
@@ -488,19 +521,6 @@ __device__ __forceinline__ double stencil_sum(const T *pl, const T (&yrow)[2 * N
         acc += kw[d] * ((double)xs + (double)ys + (double)zs);
     }
     return acc;
-}
-
-// Rows of the y legs for all RB columns of the thread: LDS for the other
-// rows, registers for the thread's own rows.
-template <int C, typename T>
-__device__ __forceinline__ void load_yrows(const T *pl, const T (&tv)[Shape<C>::RB][C], int z,
-                                           T (&yrow)[2 * NO + Shape<C>::RB]) {
-    constexpr int P = Shape<C>::P, RB = Shape<C>::RB;
-#pragma unroll
-    for (int j = 0; j < 2 * NO + RB; ++j) {
-        if (j >= NO && j < NO + RB) yrow[j] = tv[j - NO][z];
-        else yrow[j] = pl[j * P + NO];
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -593,22 +613,22 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
                     L.plane[z & 1][cl.pcw[r]] = tv[r][z];
                 }
                 __syncthreads();
-                const T *pl = L.plane[z & 1] + cl.corner;
+                const PlaneView<C, T> pv(L.plane[0], z & 1, cl.corner);
                 T yrow[2 * NO + RB];
-                load_yrows<C, T>(pl, tv, z, yrow);
+                load_yrows<C, T>(pv, tv, z, yrow);
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    const double acc = stencil_sum<C, T>(pl, yrow, tv[r], r, z, kw);
+                    const double acc = stencil_sum<C, T>(pv, yrow, tv[r], r, z, kw);
                     const double tz = (double)tv[r][z];
                     const double u = acc + (vz[r] + c0) * invz * tz;
-                    double pv[NCH];
+                    double pval[NCH];
                     double nvd = al * u - tprev[r];
 #pragma unroll
                     for (int ci = 0; ci < NCH; ++ci) {
-                        pv[ci] = 0.0;
+                        pval[ci] = 0.0;
                         if (ci == 0 || ci < nch) {
-                            pv[ci] = ch[r][ci].value(pvr, z);
-                            nvd += L.cs[ch[r][ci].sl()] * pv[ci];
+                            pval[ci] = ch[r][ci].value(pvr, z);
+                            nvd += L.cs[ch[r][ci].sl()] * pval[ci];
                         }
                     }
                     // a column past the cube edge (odd C) shares its neighbour reads
@@ -626,7 +646,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
 #pragma unroll
                     for (int ci = 0; ci < NCH; ++ci) {
                         if (ci == 0 || ci < nch) {
-                            ch[r][ci].acc += pv[ci] * nvd;
+                            ch[r][ci].acc += pval[ci] * nvd;
                             pin(ch[r][ci].acc);
                             ch[r][ci].finish(snext, z, L.runs, SENT);
                         }
@@ -710,8 +730,11 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
     Cols<C> cl;
     cl.init(tid);
     const int n = A.n;
+    // slot: v_{j-1}, overwritten by v_j during the sweep; wslot: u = H v_j - beta v_{j-1}
     const __amdgpu_buffer_rsrc_t slr =
         make_rsrc(reinterpret_cast<T *>(A.slots) + (long long)blockIdx.x * A.slot_elems, A.slot_elems * 8);
+    const __amdgpu_buffer_rsrc_t wlr =
+        make_rsrc(reinterpret_cast<T *>(A.wslots) + (long long)blockIdx.x * A.slot_elems, A.slot_elems * 8);
     const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
     const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
     unsigned voff[RB];
@@ -762,7 +785,6 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
             for (int r = 0; r < RB; ++r) chains_start(L, cl.col[r], ch[r]);
             unsigned zb = zbase;
             asm volatile("" : "+s"(zb));
-            double wv[RB][C];
             double da = 0.0;
 #pragma unroll
             for (int z = 0; z < C; ++z) {
@@ -777,25 +799,30 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
                     L.plane[z & 1][cl.pcw[r]] = tv[r][z];
                 }
                 __syncthreads();
-                const double *pl = L.plane[z & 1] + cl.corner;
+                const PlaneView<C, double> pv(L.plane[0], z & 1, cl.corner);
                 double yrow[2 * NO + RB];
-                load_yrows<C, double>(pl, tv, z, yrow);
+                load_yrows<C, double>(pv, tv, z, yrow);
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    double u = stencil_sum<C, double>(pl, yrow, tv[r], r, z, kw) + (vz[r] + kin0) * tv[r][z];
+                    double u = stencil_sum<C, double>(pv, yrow, tv[r], r, z, kw) + (vz[r] + kin0) * tv[r][z];
+                    double pval[NCH];
 #pragma unroll
                     for (int ci = 0; ci < NCH; ++ci) {
+                        pval[ci] = 0.0;
                         if (ci == 0 || ci < nch) {
-                            u += L.cs[ch[r][ci].sl()] * ch[r][ci].value(pvr, z);
-                            ch[r][ci].finish(L.s[cur ^ 1], z, L.runs, SENT);  // advance only; acc stays 0
+                            pval[ci] = ch[r][ci].value(pvr, z);
+                            u += L.cs[ch[r][ci].sl()] * pval[ci];
                         }
                     }
                     u -= bprev * vprev[r];
                     if (!cl.valid(r)) u = 0.0;  // column past the cube edge stays zero
                     bstore(tv[r][z], slr, voff[r], sz);
-                    wv[r][z] = u;
+                    bstore(u, wlr, voff[r], sz);
                     da += u * tv[r][z];
                     pin(da);
+#pragma unroll
+                    for (int ci = 0; ci < NCH; ++ci)
+                        if (ci == 0 || ci < nch) ch[r][ci].finish(L.s[cur ^ 1], z, L.runs, SENT);  // advance
                 }
             }
             __syncthreads();
@@ -803,17 +830,20 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
             block_sum2(L, da, dummy, tid);
             const double alpha = da;
 
-            // w -= alpha v;  beta = |w|;  projector dots of w
+            // w = u - alpha v (into the register columns);  beta = |w|;  p . w
+            // (taken from w itself: a projector dot carried by linearity,
+            // (p.u - alpha p.v) / beta, grows its rounding error by |alpha/beta|
+            // per step)
+            double db = 0.0;
 #pragma unroll
             for (int r = 0; r < RB; ++r) chains_start(L, cl.col[r], ch[r]);
-            double db = 0.0;
 #pragma unroll
             for (int z = 0; z < C; ++z) {
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    const double v = bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u);
-                    const double w = wv[r][z] - alpha * v;
-                    wv[r][z] = w;
+                    const unsigned sz = (unsigned)(z * S::CC) * 8u;
+                    const double w = bload<double>(wlr, voff[r], sz) - alpha * bload<double>(slr, voff[r], sz);
+                    tv[r][z] = w;
                     db += w * w;
                     pin(db);
 #pragma unroll
@@ -843,7 +873,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int z = 0; z < C; ++z) tv[r][z] = wv[r][z] * rb;
+                for (int z = 0; z < C; ++z) tv[r][z] *= rb;
             for (int i = tid; i < kMaxImages; i += S::BLOCK) {
                 L.s[cur ^ 1][i] = L.s[cur ^ 1][i] * rb;
                 L.s[cur][i] = 0.0;
