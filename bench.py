@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--workload", default="paper", choices=["paper", "paper-small", "large", "tiny"])
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1",
@@ -130,6 +132,14 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print("[bench] copy calibration: 1 GiB device-to-device", file=sys.stderr, flush=True)
     wl = workload(args.workload)
     print(f"[bench] {wl.name}: n={wl.n} natom={wl.natom} npl={wl.npl}", file=sys.stderr, flush=True)
 
