@@ -90,7 +90,8 @@ void sq_default_options(sq_options *opt);
  *   cell      cubic cell edge L (> 0)
  *   h         requested mesh size (> 0); refitted to L / round(L / h)
  *   fd_order  even order 2 n_o of the central FD Laplacian, 2..12
- *   rcut      R_cut: half-side of the cubic region of influence; m >= 1
+ *   rcut      R_cut: half-side of the cubic region of influence; 1 <= m <= 18
+ *             (cube side 2m + 1 <= 37; SQ_EINVAL beyond)
  *   npl       quadrature order n_pl, a multiple of 4 in [4, 1000]
  *   kT        smearing sigma (Ha, > 0)
  *   natom     number of atoms (>= 0)
@@ -102,6 +103,8 @@ void sq_default_options(sq_options *opt);
  *             if natom == 0
  *   opt       (host) options or NULL for the defaults
  * Host inputs are copied.  On success *ctx owns host tables only.
+ * SQ_ECAPACITY if more than four projector spheres overlap at a grid point
+ * (more than two for cubes wider than 31 points).
  */
 int sq_setup(sq_ctx **ctx, double cell, double h, int fd_order, double rcut, int npl,
              double kT, int natom, const double *atom_xyz, const double *kb,
@@ -157,6 +160,64 @@ int sq_density_energy(sq_ctx *ctx, const double *moments, double mu, double *rho
 
 /* Release the host tables (never touches caller-owned device memory). */
 void sq_destroy(sq_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Batched snapshots: one SCF pass (bounds, moments, Fermi level, density and
+ * energies at fixed V_eff, Sec. 3.2-3.3) of many independent snapshots per
+ * call, e.g. the configurations of a molecular-dynamics ensemble.  The nodes
+ * of all snapshots are cut into blocks; a persistent launch per cube size
+ * takes (snapshot, block) items from a device work queue, largest work first.
+ * The Fermi level of every snapshot is found on the device by the same Brent
+ * iteration as sq_fermi_level (bit-identical results), so a whole pass runs
+ * without host round trips and can be captured as one hipGraph.
+ * ------------------------------------------------------------------------- */
+typedef struct sq_batch sq_batch;
+
+typedef struct sq_batch_options {
+    int block_nodes;     /* nodes per work item (0: default 32, or the autotuned value) */
+    int wg_per_cu;       /* persistent workgroups per compute unit (0: occupancy limit) */
+    int use_graph;       /* 1 (default): capture the pass as a hipGraph on the first
+                            sq_batch_step and replay it afterwards; 0: plain launches */
+} sq_batch_options;
+
+void sq_batch_default_options(sq_batch_options *opt);
+
+/* Group n >= 1 contexts into a batch.  Every context must be bound (sq_bind)
+ * and all must share one precision; they are borrowed and must outlive the
+ * batch.  moments[i] (device, N_d x (n_pl + 1) FP64) and rho[i] (device, N_d
+ * FP64) receive snapshot i's results; n_electrons[i] (host) is its N_e.
+ * Pointers are copied.  SQ_ECAPACITY if a context needs four projector chains
+ * on a cube wider than 31 points. */
+int sq_batch_create(sq_batch **batch, sq_ctx *const *ctxs, int n, double *const *moments,
+                    double *const *rho, const double *n_electrons, const sq_batch_options *opt);
+
+/* Device workspace the batch needs (work queues, per-workgroup vector
+ * buffers sized for the largest cube, Fermi-level state). */
+int sq_batch_query(const sq_batch *batch, size_t *workspace_bytes);
+
+/* Bind a caller-allocated device workspace (256-byte aligned) and upload the
+ * work queues.  Synchronises `stream`. */
+int sq_batch_bind(sq_batch *batch, void *workspace, size_t bytes, void *stream);
+
+/* One pass of every snapshot at its current V_eff.  mu (host, n) and energies
+ * (host, n x 4, as in sq_density_energy) receive the results.  The pass runs
+ * on a private stream ordered after `stream`; `stream` waits for it.
+ * Synchronises.  Per-snapshot failures are reported as for the single-snapshot
+ * calls (the first failing snapshot's status and message). */
+int sq_batch_step(sq_batch *batch, double *mu, double *energies, void *stream);
+
+/* Time the candidate tile shapes (block_nodes x wg_per_cu) on a sample of
+ * every snapshot's nodes and keep the fastest; with cache_path (host, may be
+ * NULL) the choice is read from / appended to that JSON file, keyed by the
+ * device and the batch's cube sizes and precision.  Invalidates a captured
+ * graph.  Synchronises `stream`. */
+int sq_batch_autotune(sq_batch *batch, const char *cache_path, void *stream);
+
+/* Chosen tile shape and the number of work items of the current queues. */
+int sq_batch_tiles(const sq_batch *batch, int *block_nodes, int *wg_per_cu, int *n_items);
+
+/* Release host state and the private stream and graph. */
+void sq_batch_destroy(sq_batch *batch);
 
 /* Message for the last failure on the calling thread ("" if none). */
 const char *sq_last_error(void);

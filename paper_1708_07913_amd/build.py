@@ -25,14 +25,17 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                "-munsafe-fp-atomics"]
+                "-munsafe-fp-atomics",
+                # the plane loops of the recurrence kernels must unroll fully
+                # (register-resident columns are indexed by plane)
+                "-mllvm", "-pragma-unroll-threshold=1000000"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__",
               "-I/opt/rocm/include"]
 CXX = os.environ.get("CXX", "g++")
 
 # recurrence kernels are split into several translation units by cube size so
 # that the build parallelises
-CUBE_GROUPS = [[3, 5, 7, 9, 11, 13], [15, 17, 19], [21, 23], [25, 27], [29], [31]]
+CUBE_GROUPS = [[3, 5, 7, 9, 11, 13], [15, 17, 19], [21, 23], [25, 27], [29], [31], [33], [35], [37]]
 
 
 def _run(cmd):

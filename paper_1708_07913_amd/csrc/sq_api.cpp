@@ -64,7 +64,8 @@ struct sq_ctx {
     int max_overlap = 0;
     size_t off_atoms = 0, off_runs = 0, off_pvals = 0, off_chi = 0, off_zeta = 0, off_ctab = 0,
            off_rk = 0, off_W = 0, off_part = 0, off_scal = 0, off_flags = 0, off_v32 = 0,
-           off_slots = 0, off_wslots = 0, total = 0;
+           off_slots = 0, off_wslots = 0, off_xslots = 0, off_args = 0, total = 0;
+    sq::RecurrenceArgs args_host[2] = {};  // staged launch arguments (Lanczos, moments)
     char *ws = nullptr;
     const double *veff = nullptr;
     int state = kSetup;
@@ -164,6 +165,15 @@ int hip_check(hipError_t e, const char *what) {
     return fail(SQ_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+int flags_status(int flags) {
+    if (flags & sq::kFlagImages) return fail(SQ_ECAPACITY, "more projector images in a region than supported");
+    if (flags & sq::kFlagRuns) return fail(SQ_ECAPACITY, "projector run table of a region overflowed");
+    if (flags & sq::kFlagOverlap) return fail(SQ_ECAPACITY, "more than two projector spheres overlap");
+    if (flags & sq::kFlagLanczos) return fail(SQ_EINVAL, "non-finite Lanczos coefficient (check V_eff)");
+    if (flags & sq::kFlagBounds) return fail(SQ_EBOUNDS, "a Chebyshev moment left [-1, 1]: bounds too tight");
+    return SQ_OK;
+}
+
 int read_flags(sq_ctx *c, hipStream_t s) {
     int flags = 0;
     int rc = hip_check(hipMemcpyAsync(&flags, c->at<int>(c->off_flags), sizeof(int), hipMemcpyDeviceToHost, s),
@@ -171,12 +181,7 @@ int read_flags(sq_ctx *c, hipStream_t s) {
     if (rc) return rc;
     rc = hip_check(hipStreamSynchronize(s), "kernel execution");
     if (rc) return rc;
-    if (flags & sq::kFlagImages) return fail(SQ_ECAPACITY, "more projector images in a region than supported");
-    if (flags & sq::kFlagRuns) return fail(SQ_ECAPACITY, "projector run table of a region overflowed");
-    if (flags & sq::kFlagOverlap) return fail(SQ_ECAPACITY, "more than two projector spheres overlap");
-    if (flags & sq::kFlagLanczos) return fail(SQ_EINVAL, "non-finite Lanczos coefficient (check V_eff)");
-    if (flags & sq::kFlagBounds) return fail(SQ_EBOUNDS, "a Chebyshev moment left [-1, 1]: bounds too tight");
-    return SQ_OK;
+    return flags_status(flags);
 }
 
 sq::RecurrenceArgs recurrence_args(sq_ctx *c) {
@@ -196,9 +201,6 @@ sq::RecurrenceArgs recurrence_args(sq_ctx *c) {
     a.chi = c->at<double>(c->off_chi);
     a.zeta = c->at<double>(c->off_zeta);
     a.npl = c->npl;
-    a.slots = c->ws + c->off_slots;
-    a.wslots = c->ws + c->off_wslots;
-    a.slot_elems = c->ns;
     a.flags = c->at<int>(c->off_flags);
     a.nch = c->nch;
     a.n_lanczos = c->opt.n_lanczos;
@@ -206,6 +208,24 @@ sq::RecurrenceArgs recurrence_args(sq_ctx *c) {
     a.margin = c->opt.margin;
     a.bounds_tol = c->opt.precision == SQ_FP32_MIXED ? 1e-5 : 1e-10;
     return a;
+}
+
+// Stage the arguments of one recurrence launch in the workspace (kernels read
+// them from device memory) and describe the launch: every node of this
+// snapshot, split statically over the XCDs.
+int stage_launch(sq_ctx *c, const sq::RecurrenceArgs &a, int which, hipStream_t s, sq::LaunchArgs *k) {
+    c->args_host[which] = a;
+    sq::RecurrenceArgs *dev = c->at<sq::RecurrenceArgs>(c->off_args) + which;
+    int rc = hip_check(hipMemcpyAsync(dev, &c->args_host[which], sizeof(a), hipMemcpyHostToDevice, s),
+                       "staging launch arguments");
+    if (rc) return rc;
+    *k = sq::LaunchArgs{};
+    k->snaps = dev;
+    k->slots = c->ws + c->off_slots;
+    k->wslots = c->ws + c->off_wslots;
+    k->xslots = c->ws + c->off_xslots;
+    k->slot_elems = c->ns;
+    return SQ_OK;
 }
 
 int pick_workgroups(sq_ctx *c) {
@@ -253,9 +273,14 @@ void layout(sq_ctx *c) {
     c->off_part = take(3 * kReduceBlocks * sizeof(double));
     c->off_scal = take(8 * sizeof(double));
     c->off_flags = take(64);
+    c->off_args = take(2 * sizeof(sq::RecurrenceArgs));
     c->off_v32 = take(c->opt.precision == SQ_FP32_MIXED ? size_t(c->nd) * sizeof(float) : 0);
     c->off_slots = take(size_t(c->nwg_slots) * size_t(c->ns) * sizeof(double));
-    c->off_wslots = take(size_t(c->nwg_lanczos) * size_t(c->ns) * sizeof(double));
+    // streamed regions (wider than kResidentCube) need a second buffer in the
+    // moments sweep and a third in Lanczos
+    const bool stream = c->C > sq::kResidentCube;
+    c->off_wslots = take(size_t(stream ? c->nwg_slots : c->nwg_lanczos) * size_t(c->ns) * sizeof(double));
+    c->off_xslots = take(stream ? size_t(c->nwg_lanczos) * size_t(c->ns) * sizeof(double) : 0);
     c->total = off;
 }
 
@@ -306,6 +331,337 @@ int guarded(F f) {
         return fail(SQ_ENOMEM, "host allocation failed");
     } catch (...) {
         return fail(SQ_EINVAL, "unexpected host exception");
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batched snapshots
+// ---------------------------------------------------------------------------
+struct sq_batch {
+    struct Group {
+        int C = 0, nch = 2;
+        std::vector<int> snaps;
+        int occ_l = 1, occ_m = 1;   // resident workgroups per CU (Lanczos, moments)
+        int item0 = 0, n_items = 0; // range in the item table
+    };
+    std::vector<sq_ctx *> ctx;
+    std::vector<double *> moments, rho;
+    std::vector<double> n_e;
+    sq_batch_options opt{};
+    bool mixed = false;
+    int device = 0, cus = 0, max_brent = 200;
+    char device_name[256] = {0};
+    std::vector<Group> groups;
+    long long max_ns = 0;
+    int nwg_cap = 0;                 // largest grid of any launch (buffers are sized for it)
+    int block_nodes = 32, wg_per_cu = 0;
+    std::vector<sq::WorkItem> items;
+    std::vector<sq::RecurrenceArgs> args;
+    std::vector<sq::FermiSnap> fermi;
+    std::vector<sq::BrentParams> prm;
+    std::vector<sq::BrentState> state_host;
+    std::vector<double> scal_host;
+    std::vector<int> flags_host;
+    size_t off_args = 0, off_items = 0, off_counters = 0, off_fermi = 0, off_prm = 0, off_state = 0, off_ext = 0,
+           off_part = 0, off_slots = 0, off_wslots = 0, off_xslots = 0, total = 0;
+    size_t items_capacity = 0;
+    char *ws = nullptr;
+    hipStream_t own = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    template <typename T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    ~sq_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (own) (void)hipStreamDestroy(own);
+    }
+};
+
+namespace {
+
+void drop_graph(sq_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+int batch_grid(const sq_batch *b, const sq_batch::Group &g, bool lanczos) {
+    const int occ = lanczos ? g.occ_l : g.occ_m;
+    const int per_cu = b->wg_per_cu > 0 ? std::min(b->wg_per_cu, occ) : occ;
+    return std::max(1, std::min(g.n_items, b->cus * per_cu));
+}
+
+// Work items: blocks of block_nodes consecutive nodes of the first
+// `fraction` of every snapshot's nodes; per group, the most expensive
+// snapshots (per-node cost ~ N_s (n_lanczos + n_pl / 2)) first.
+void build_items(sq_batch *b, int block_nodes, double fraction) {
+    b->items.clear();
+    for (auto &g : b->groups) {
+        g.item0 = int(b->items.size());
+        std::vector<int> order = g.snaps;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            const sq_ctx *a = b->ctx[size_t(x)], *c = b->ctx[size_t(y)];
+            return a->opt.n_lanczos * 2 + a->npl > c->opt.n_lanczos * 2 + c->npl;
+        });
+        for (int si : order) {
+            const sq_ctx *c = b->ctx[size_t(si)];
+            const long long nodes = std::max<long long>(1, (long long)std::ceil(double(c->nd) * fraction));
+            for (long long q = 0; q < std::min(nodes, c->nd); q += block_nodes) {
+                sq::WorkItem it{};
+                it.snap = si;
+                it.q0 = q;
+                it.q1 = std::min({q + block_nodes, nodes, c->nd});
+                b->items.push_back(it);
+            }
+        }
+        g.n_items = int(b->items.size()) - g.item0;
+    }
+}
+
+int upload_items(sq_batch *b, hipStream_t s) {
+    if (b->items.size() > b->items_capacity) return fail(SQ_ENOMEM, "work-item table larger than its workspace region");
+    return hip_check(hipMemcpyAsync(b->at<sq::WorkItem>(b->off_items), b->items.data(),
+                                    b->items.size() * sizeof(sq::WorkItem), hipMemcpyHostToDevice, s),
+                     "uploading work items");
+}
+
+// Snapshot arguments are re-staged before every pass: V_eff may have been
+// replaced (sq_update_veff) since the previous one.
+int upload_args(sq_batch *b, hipStream_t s) {
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        b->args[i] = recurrence_args(b->ctx[i]);
+        b->args[i].moments = b->moments[i];
+    }
+    return hip_check(hipMemcpyAsync(b->at<sq::RecurrenceArgs>(b->off_args), b->args.data(),
+                                    b->args.size() * sizeof(sq::RecurrenceArgs), hipMemcpyHostToDevice, s),
+                     "staging snapshot arguments");
+}
+
+sq::LaunchArgs group_launch(sq_batch *b, const sq_batch::Group &g, int counter) {
+    sq::LaunchArgs k{};
+    k.snaps = b->at<sq::RecurrenceArgs>(b->off_args);
+    k.items = b->at<sq::WorkItem>(b->off_items) + g.item0;
+    k.n_items = g.n_items;
+    k.counter = b->at<int>(b->off_counters) + counter;
+    k.slots = b->ws + b->off_slots;
+    k.wslots = b->ws + b->off_wslots;
+    k.xslots = b->ws + b->off_xslots;
+    k.slot_elems = b->max_ns;
+    return k;
+}
+
+int enqueue_recurrences(sq_batch *b, bool lanczos, bool moments, hipStream_t s) {
+    const int ng = int(b->groups.size());
+    int rc = hip_check(sq::launch_zero_ints(b->at<int>(b->off_counters), 2 * ng, s), "clearing work queues");
+    if (rc) return rc;
+    for (sq_ctx *c : b->ctx) {
+        rc = hip_check(sq::launch_zero_ints(c->at<int>(c->off_flags), 1, s), "clearing flags");
+        if (rc) return rc;
+    }
+    for (int gi = 0; lanczos && gi < ng; ++gi) {
+        const auto &g = b->groups[size_t(gi)];
+        if (g.n_items == 0) continue;
+        rc = hip_check(sq::launch_lanczos(group_launch(b, g, 2 * gi), g.C, g.nch, batch_grid(b, g, true), s),
+                       "launching batched Lanczos");
+        if (rc) return rc;
+    }
+    for (int gi = 0; moments && gi < ng; ++gi) {
+        const auto &g = b->groups[size_t(gi)];
+        if (g.n_items == 0) continue;
+        rc = hip_check(sq::launch_moments(group_launch(b, g, 2 * gi + 1), g.C, g.nch, b->mixed,
+                                          batch_grid(b, g, false), s),
+                       "launching batched moments");
+        if (rc) return rc;
+    }
+    return SQ_OK;
+}
+
+// The whole pass, without host round trips (so that it can be captured).
+int enqueue_pass(sq_batch *b, hipStream_t s) {
+    int rc = enqueue_recurrences(b, true, true, s);
+    if (rc) return rc;
+    const int n = int(b->ctx.size());
+    for (int i = 0; i < n; ++i) {
+        sq_ctx *c = b->ctx[size_t(i)];
+        rc = hip_check(sq::launch_quadrature_weights(b->moments[size_t(i)], c->at<double>(c->off_ctab),
+                                                     c->at<double>(c->off_W), c->nd, c->npl, s),
+                       "quadrature weights");
+        if (rc) return rc;
+        rc = hip_check(sq::launch_extent(c->at<double>(c->off_chi), c->at<double>(c->off_zeta), c->nd,
+                                         c->at<double>(c->off_part), kReduceBlocks, b->at<double>(b->off_ext) + 2 * i,
+                                         s),
+                       "spectral extent");
+        if (rc) return rc;
+    }
+    sq::BrentState *st = b->at<sq::BrentState>(b->off_state);
+    rc = hip_check(sq::launch_brent_begin(st, b->at<sq::BrentParams>(b->off_prm), b->at<double>(b->off_ext), n, s),
+                   "Fermi level");
+    if (rc) return rc;
+    // two bracket evaluations, then at most max_brent iterations
+    for (int it = 0; it < b->max_brent + 2; ++it) {
+        rc = hip_check(sq::launch_count_batch(b->at<sq::FermiSnap>(b->off_fermi), st, n, b->at<double>(b->off_part),
+                                              kReduceBlocks, s),
+                       "electron count");
+        if (rc) return rc;
+        rc = hip_check(sq::launch_brent_feed(st, b->at<double>(b->off_part), kReduceBlocks, n, s), "Brent step");
+        if (rc) return rc;
+    }
+    for (int i = 0; i < n; ++i) {
+        sq_ctx *c = b->ctx[size_t(i)];
+        const double h3 = c->h * c->h * c->h;
+        rc = hip_check(sq::launch_density(c->at<double>(c->off_W), c->at<double>(c->off_chi),
+                                          c->at<double>(c->off_zeta), c->at<double>(c->off_rk), c->nd, c->nq, 0.0,
+                                          &st[i].xb, c->kT, h3, b->rho[size_t(i)], c->at<double>(c->off_part),
+                                          kReduceBlocks, c->at<double>(c->off_scal), s),
+                       "density");
+        if (rc) return rc;
+    }
+    return SQ_OK;
+}
+
+// Collect the per-snapshot results of a pass (after it was enqueued on s).
+int finish_pass(sq_batch *b, hipStream_t s, double *mu, double *energies) {
+    const size_t n = b->ctx.size();
+    int rc = hip_check(hipMemcpyAsync(b->state_host.data(), b->at<sq::BrentState>(b->off_state),
+                                      n * sizeof(sq::BrentState), hipMemcpyDeviceToHost, s),
+                       "reading Fermi levels");
+    for (size_t i = 0; !rc && i < n; ++i) {
+        sq_ctx *c = b->ctx[i];
+        rc = hip_check(hipMemcpyAsync(&b->scal_host[3 * i], c->at<double>(c->off_scal), 3 * sizeof(double),
+                                      hipMemcpyDeviceToHost, s),
+                       "reading energies");
+        if (!rc)
+            rc = hip_check(hipMemcpyAsync(&b->flags_host[i], c->at<int>(c->off_flags), sizeof(int),
+                                          hipMemcpyDeviceToHost, s),
+                           "reading device flags");
+    }
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "batched pass");
+    if (rc) return rc;
+    int first = SQ_OK;
+    std::string msg;
+    for (size_t i = 0; i < n; ++i) {
+        sq_ctx *c = b->ctx[i];
+        int st = flags_status(b->flags_host[i]);
+        const sq::BrentState &bs = b->state_host[i];
+        if (!st && bs.phase != sq::kBrentDone) {
+            st = fail(SQ_ENOCONV, bs.phase == sq::kBrentNonFinite ? "non-finite electron count"
+                                  : bs.phase == sq::kBrentNoSign
+                                      ? "electron count does not change sign over the spectral bracket"
+                                      : "Fermi level search did not converge");
+        }
+        if (st) {
+            if (!first) {
+                first = st;
+                msg = "snapshot " + std::to_string(i) + ": " + g_error;
+            }
+            continue;
+        }
+        c->state = kBounds;
+        const double h3 = c->h * c->h * c->h;
+        if (mu) mu[i] = bs.xb;
+        if (energies) {
+            energies[4 * i] = b->scal_host[3 * i];
+            energies[4 * i + 1] = b->scal_host[3 * i + 1];
+            energies[4 * i + 2] = b->scal_host[3 * i] + b->scal_host[3 * i + 1];
+            energies[4 * i + 3] = h3 * b->scal_host[3 * i + 2];
+        }
+    }
+    if (first) return fail(first, msg);
+    return SQ_OK;
+}
+
+int batch_layout(sq_batch *b) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    const size_t n = b->ctx.size(), ng = b->groups.size();
+    // the item table must hold the smallest block size the tuner tries
+    size_t cap = 0;
+    for (sq_ctx *c : b->ctx) cap += size_t((c->nd + 7) / 8);
+    b->items_capacity = cap;
+    b->off_args = take(n * sizeof(sq::RecurrenceArgs));
+    b->off_items = take(cap * sizeof(sq::WorkItem));
+    b->off_counters = take(2 * ng * sizeof(int));
+    b->off_fermi = take(n * sizeof(sq::FermiSnap));
+    b->off_prm = take(n * sizeof(sq::BrentParams));
+    b->off_state = take(n * sizeof(sq::BrentState));
+    b->off_ext = take(2 * n * sizeof(double));
+    b->off_part = take(n * size_t(kReduceBlocks) * sizeof(double));
+    const size_t slot = size_t(b->nwg_cap) * size_t(b->max_ns) * sizeof(double);
+    bool stream = false;
+    for (const auto &g : b->groups) stream = stream || g.C > sq::kResidentCube;
+    b->off_slots = take(slot);
+    b->off_wslots = take(slot);
+    b->off_xslots = take(stream ? slot : 0);
+    b->total = off;
+    return SQ_OK;
+}
+
+// Autotuner cache: a flat JSON object {"key": {"block_nodes": B, "wg_per_cu": W, "ms": T}, ...}.
+std::string tune_key(const sq_batch *b) {
+    std::vector<std::string> parts;
+    for (const auto &g : b->groups) {
+        long long nodes = 0;
+        for (int si : g.snaps) nodes += b->ctx[size_t(si)]->nd;
+        parts.push_back("C" + std::to_string(g.C) + "x" + std::to_string(g.nch) + ":" + std::to_string(nodes));
+    }
+    std::sort(parts.begin(), parts.end());
+    std::string key = std::string(b->device_name) + "/" + std::to_string(b->cus) + "cu/" + (b->mixed ? "mixed" : "fp64");
+    for (const auto &p : parts) key += "/" + p;
+    return key;
+}
+
+bool cache_lookup(const char *path, const std::string &key, int *block, int *wg) {
+    if (!path) return false;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return false;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    const size_t at = text.find("\"" + key + "\"");
+    if (at == std::string::npos) return false;
+    const size_t pb = text.find("\"block_nodes\":", at), pw = text.find("\"wg_per_cu\":", at);
+    if (pb == std::string::npos || pw == std::string::npos) return false;
+    return std::sscanf(text.c_str() + pb + 14, "%d", block) == 1 && std::sscanf(text.c_str() + pw + 12, "%d", wg) == 1;
+}
+
+void cache_store(const char *path, const std::string &key, int block, int wg, double ms) {
+    if (!path) return;
+    std::string text;
+    if (FILE *f = std::fopen(path, "rb")) {
+        char buf[4096];
+        size_t got;
+        while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+        std::fclose(f);
+    }
+    const size_t close = text.rfind('}');
+    char entry[512];
+    std::snprintf(entry, sizeof(entry), "\"%s\": {\"block_nodes\": %d, \"wg_per_cu\": %d, \"ms\": %.3f}", key.c_str(),
+                  block, wg, ms);
+    std::string out;
+    if (close == std::string::npos || text.find('{') == std::string::npos) {
+        out = std::string("{\n ") + entry + "\n}\n";
+    } else {
+        std::string head = text.substr(0, close);
+        while (!head.empty() && (head.back() == '\n' || head.back() == ' ')) head.pop_back();
+        out = head + (head.back() == '{' ? "\n " : ",\n ") + entry + "\n}\n";
+    }
+    if (FILE *f = std::fopen(path, "wb")) {
+        std::fwrite(out.data(), 1, out.size(), f);
+        std::fclose(f);
     }
 }
 
@@ -365,7 +721,7 @@ int sq_setup(sq_ctx **ctx, double cell, double h, int fd_order, double rcut, int
         c->m = int(mreal);
         c->C = 2 * c->m + 1;
         if (c->C > sq::kMaxCube || sq::recurrence_block(c->C) == 0)
-            return fail(SQ_EINVAL, "region of influence wider than 31 grid points is not supported");
+            return fail(SQ_EINVAL, "region of influence wider than 37 grid points is not supported");
         c->npl = npl;
         c->nq = npl + 1;
         c->kT = kT;
@@ -407,6 +763,8 @@ int sq_setup(sq_ctx **ctx, double cell, double h, int fd_order, double rcut, int
                 }
             if (c->max_overlap > 4)
                 return fail(SQ_ECAPACITY, "more than four projector spheres overlap at a grid point");
+            if (c->max_overlap > 2 && c->C > sq::kResidentCube)
+                return fail(SQ_ECAPACITY, "regions wider than 31 points support at most two overlapping projector spheres");
             c->nch = c->max_overlap > 2 ? 4 : 2;
         }
         // discrete-orthogonality table on N_q = n_pl + 1 Chebyshev-Gauss nodes
@@ -486,7 +844,10 @@ int sq_spectral_bounds(sq_ctx *c, double *lmin, double *lmax, void *stream) {
         sq::RecurrenceArgs a = recurrence_args(c);
         a.lmin = lmin;
         a.lmax = lmax;
-        rc = hip_check(sq::launch_lanczos(a, c->nwg_lanczos, s), "launching Lanczos");
+        sq::LaunchArgs k;
+        rc = stage_launch(c, a, 0, s, &k);
+        if (rc) return rc;
+        rc = hip_check(sq::launch_lanczos(k, c->C, c->nch, c->nwg_lanczos, s), "launching Lanczos");
         if (rc) return rc;
         rc = read_flags(c, s);
         if (rc) return rc;
@@ -517,7 +878,10 @@ int sq_moments(sq_ctx *c, double *moments, void *stream) {
         if (rc) return rc;
         sq::RecurrenceArgs a = recurrence_args(c);
         a.moments = moments;
-        rc = hip_check(sq::launch_moments(a, c->opt.precision == SQ_FP32_MIXED, c->nwg_moments, s),
+        sq::LaunchArgs k;
+        rc = stage_launch(c, a, 1, s, &k);
+        if (rc) return rc;
+        rc = hip_check(sq::launch_moments(k, c->C, c->nch, c->opt.precision == SQ_FP32_MIXED, c->nwg_moments, s),
                        "launching moments");
         if (rc) return rc;
         return read_flags(c, s);
@@ -544,67 +908,24 @@ int sq_fermi_level(sq_ctx *c, const double *moments, double n_electrons, double 
         rc = device_scalars(c, s, ext, 2);
         if (rc) return rc;
         // Brent's method (inverse quadratic interpolation, secant, bisection)
-        // on f(mu) = N(mu) - N_e over the spectral bracket.
-        double xa = ext[0] - 40.0 * c->kT, xb = ext[1] + 40.0 * c->kT;
-        double fa, fb;
-        rc = electron_count(c, xa, s, &fa);
-        if (rc) return rc;
-        rc = electron_count(c, xb, s, &fb);
-        if (rc) return rc;
-        fa -= n_electrons;
-        fb -= n_electrons;
-        if (!(is_finite(fa) && is_finite(fb))) return fail(SQ_ENOCONV, "non-finite electron count");
-        if ((fa > 0) == (fb > 0) && fa != 0 && fb != 0)
-            return fail(SQ_ENOCONV, "electron count does not change sign over the spectral bracket");
-        const double ftol = c->opt.ne_rtol * n_electrons;
-        double xc = xa, fc = fa, step = xb - xa, prev_step = step;
-        for (int it = 0; it < c->opt.max_brent; ++it) {
-            if ((fb > 0 && fc > 0) || (fb < 0 && fc < 0)) {  // keep the root between xb and xc
-                xc = xa;
-                fc = fa;
-                step = prev_step = xb - xa;
-            }
-            if (std::fabs(fc) < std::fabs(fb)) {  // xb is the best estimate
-                xa = xb; xb = xc; xc = xa;
-                fa = fb; fb = fc; fc = fa;
-            }
-            const double tol = 2.0 * std::numeric_limits<double>::epsilon() * std::fabs(xb) + 0.5 * c->opt.mu_xtol;
-            const double half = 0.5 * (xc - xb);
-            if (std::fabs(half) <= tol || std::fabs(fb) <= ftol || fb == 0.0) {
-                *mu = xb;
-                return SQ_OK;
-            }
-            if (std::fabs(prev_step) >= tol && std::fabs(fa) > std::fabs(fb)) {
-                const double sb = fb / fa;
-                double p, q;
-                if (xa == xc) {  // secant
-                    p = 2.0 * half * sb;
-                    q = 1.0 - sb;
-                } else {  // inverse quadratic interpolation
-                    const double qa = fa / fc, rb = fb / fc;
-                    p = sb * (2.0 * half * qa * (qa - rb) - (xb - xa) * (rb - 1.0));
-                    q = (qa - 1.0) * (rb - 1.0) * (sb - 1.0);
-                }
-                if (p > 0) q = -q;
-                else p = -p;
-                if (2.0 * p < 3.0 * half * q - std::fabs(tol * q) && p < std::fabs(0.5 * prev_step * q)) {
-                    prev_step = step;
-                    step = p / q;
-                } else {
-                    step = half;
-                    prev_step = step;
-                }
-            } else {
-                step = half;
-                prev_step = step;
-            }
-            xa = xb;
-            fa = fb;
-            xb += std::fabs(step) > tol ? step : (half > 0 ? tol : -tol);
-            rc = electron_count(c, xb, s, &fb);
+        // on f(mu) = N(mu) - N_e over the spectral bracket; the same state
+        // machine runs on the device for batched snapshots.
+        sq::BrentState b;
+        sq::brent_begin(b, ext[0], ext[1], c->kT, n_electrons, c->opt.mu_xtol, c->opt.ne_rtol * n_electrons,
+                        c->opt.max_brent);
+        while (b.phase >= sq::kBrentLow && b.phase <= sq::kBrentIterate) {
+            double count = 0.0;
+            rc = electron_count(c, b.mu_eval, s, &count);
             if (rc) return rc;
-            fb -= n_electrons;
+            sq::brent_feed(b, count);
         }
+        if (b.phase == sq::kBrentDone) {
+            *mu = b.xb;
+            return SQ_OK;
+        }
+        if (b.phase == sq::kBrentNonFinite) return fail(SQ_ENOCONV, "non-finite electron count");
+        if (b.phase == sq::kBrentNoSign)
+            return fail(SQ_ENOCONV, "electron count does not change sign over the spectral bracket");
         return fail(SQ_ENOCONV, "Fermi level search did not converge");
     });
 }
@@ -623,7 +944,7 @@ int sq_density_energy(sq_ctx *c, const double *moments, double mu, double *rho, 
         const double h3 = c->h * c->h * c->h;
         rc = hip_check(sq::launch_density(c->at<double>(c->off_W), c->at<double>(c->off_chi),
                                           c->at<double>(c->off_zeta), c->at<double>(c->off_rk), c->nd, c->nq, mu,
-                                          c->kT, h3, rho, c->at<double>(c->off_part), kReduceBlocks,
+                                          nullptr, c->kT, h3, rho, c->at<double>(c->off_part), kReduceBlocks,
                                           c->at<double>(c->off_scal), s),
                        "density");
         if (rc) return rc;
@@ -639,5 +960,250 @@ int sq_density_energy(sq_ctx *c, const double *moments, double mu, double *rho, 
 }
 
 void sq_destroy(sq_ctx *c) { delete c; }
+
+void sq_batch_default_options(sq_batch_options *opt) {
+    if (!opt) return;
+    opt->block_nodes = 0;
+    opt->wg_per_cu = 0;
+    opt->use_graph = 1;
+}
+
+int sq_batch_create(sq_batch **out, sq_ctx *const *ctxs, int n, double *const *moments, double *const *rho,
+                    const double *n_electrons, const sq_batch_options *opt) {
+    return guarded([&]() -> int {
+        if (!out) return fail(SQ_EINVAL, "batch out pointer is null");
+        *out = nullptr;
+        if (!ctxs || n < 1) return fail(SQ_EINVAL, "a batch needs n >= 1 contexts");
+        if (!moments || !rho || !n_electrons) return fail(SQ_EINVAL, "moments, rho and n_electrons arrays are required");
+        auto b = std::unique_ptr<sq_batch>(new sq_batch());
+        sq_batch_default_options(&b->opt);
+        if (opt) b->opt = *opt;
+        if (b->opt.block_nodes < 0 || b->opt.wg_per_cu < 0) return fail(SQ_EINVAL, "invalid batch options");
+        for (int i = 0; i < n; ++i) {
+            sq_ctx *c = ctxs[i];
+            int rc = check_ctx(c, kBound);
+            if (rc) return rc;
+            if (!moments[i] || !rho[i]) return fail(SQ_EINVAL, "moments[i] and rho[i] must be device pointers");
+            if (!(is_finite(n_electrons[i]) && n_electrons[i] > 0 && n_electrons[i] < 2.0 * double(c->nd)))
+                return fail(SQ_EINVAL, "n_electrons[i] must lie in (0, 2 N_d)");
+            const bool mixed = c->opt.precision == SQ_FP32_MIXED;
+            if (i == 0) b->mixed = mixed;
+            else if (mixed != b->mixed) return fail(SQ_EINVAL, "all contexts of a batch must share one precision");
+            if (c->C > sq::kResidentCube && c->nch > 2)
+                return fail(SQ_ECAPACITY, "regions wider than 31 points support at most two overlapping projector spheres");
+            b->ctx.push_back(c);
+            b->moments.push_back(moments[i]);
+            b->rho.push_back(rho[i]);
+            b->n_e.push_back(n_electrons[i]);
+            b->max_brent = i == 0 ? c->opt.max_brent : std::max(b->max_brent, c->opt.max_brent);
+            b->max_ns = std::max(b->max_ns, c->ns);
+            // one launch per cube side and chain count
+            auto g = std::find_if(b->groups.begin(), b->groups.end(),
+                                  [&](const sq_batch::Group &x) { return x.C == c->C && x.nch == c->nch; });
+            if (g == b->groups.end()) {
+                sq_batch::Group ng;
+                ng.C = c->C;
+                ng.nch = c->nch;
+                b->groups.push_back(ng);
+                g = b->groups.end() - 1;
+            }
+            g->snaps.push_back(i);
+        }
+        int rc = hip_check(hipGetDevice(&b->device), "hipGetDevice");
+        if (rc) return rc;
+        rc = hip_check(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device), "CU count");
+        if (rc) return rc;
+        hipDeviceProp_t prop;
+        rc = hip_check(hipGetDeviceProperties(&prop, b->device), "device properties");
+        if (rc) return rc;
+        std::snprintf(b->device_name, sizeof(b->device_name), "%s", prop.gcnArchName);
+        for (auto &g : b->groups) {
+            rc = hip_check(sq::recurrence_occupancy(g.C, true, false, g.nch, &g.occ_l), "occupancy (Lanczos)");
+            if (!rc) rc = hip_check(sq::recurrence_occupancy(g.C, false, b->mixed, g.nch, &g.occ_m), "occupancy (moments)");
+            if (rc) return rc;
+            if (g.occ_l < 1 || g.occ_m < 1) return fail(SQ_EDEVICE, "recurrence kernel does not fit on a compute unit");
+            b->nwg_cap = std::max({b->nwg_cap, b->cus * g.occ_l, b->cus * g.occ_m});
+        }
+        b->block_nodes = b->opt.block_nodes > 0 ? b->opt.block_nodes : 32;
+        b->wg_per_cu = b->opt.wg_per_cu;
+        build_items(b.get(), b->block_nodes, 1.0);
+        b->args.resize(size_t(n));
+        b->fermi.resize(size_t(n));
+        b->prm.resize(size_t(n));
+        b->state_host.resize(size_t(n));
+        b->scal_host.resize(3 * size_t(n));
+        b->flags_host.resize(size_t(n));
+        for (int i = 0; i < n; ++i) {
+            sq_ctx *c = b->ctx[size_t(i)];
+            sq::BrentParams &p = b->prm[size_t(i)];
+            p.kT = c->kT;
+            p.n_e = b->n_e[size_t(i)];
+            p.xtol = c->opt.mu_xtol;
+            p.ftol = c->opt.ne_rtol * b->n_e[size_t(i)];
+            p.max_it = c->opt.max_brent;
+        }
+        batch_layout(b.get());
+        rc = hip_check(hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking), "creating the batch stream");
+        if (!rc) rc = hip_check(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming), "creating events");
+        if (!rc) rc = hip_check(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming), "creating events");
+        if (rc) return rc;
+        *out = b.release();
+        return SQ_OK;
+    });
+}
+
+int sq_batch_query(const sq_batch *b, size_t *bytes) {
+    if (!b) return fail(SQ_EINVAL, "null batch");
+    if (bytes) *bytes = b->total;
+    return SQ_OK;
+}
+
+int sq_batch_bind(sq_batch *b, void *workspace, size_t bytes, void *stream) {
+    return guarded([&]() -> int {
+        if (!b) return fail(SQ_EINVAL, "null batch");
+        if (!workspace) return fail(SQ_EINVAL, "workspace must be a device pointer");
+        if (bytes < b->total) return fail(SQ_ENOMEM, "workspace smaller than sq_batch_query's workspace_bytes");
+        if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(SQ_EINVAL, "workspace must be 256-byte aligned");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        drop_graph(b);
+        b->ws = static_cast<char *>(workspace);
+        for (size_t i = 0; i < b->ctx.size(); ++i) {
+            sq_ctx *c = b->ctx[i];
+            sq::FermiSnap &f = b->fermi[i];
+            f.W = c->at<double>(c->off_W);
+            f.chi = c->at<double>(c->off_chi);
+            f.zeta = c->at<double>(c->off_zeta);
+            f.rk = c->at<double>(c->off_rk);
+            f.nd = c->nd;
+            f.nq = c->nq;
+            f.kT = c->kT;
+        }
+        int rc = hip_check(hipMemcpyAsync(b->at<sq::FermiSnap>(b->off_fermi), b->fermi.data(),
+                                          b->fermi.size() * sizeof(sq::FermiSnap), hipMemcpyHostToDevice, s),
+                           "uploading batch tables");
+        if (!rc)
+            rc = hip_check(hipMemcpyAsync(b->at<sq::BrentParams>(b->off_prm), b->prm.data(),
+                                          b->prm.size() * sizeof(sq::BrentParams), hipMemcpyHostToDevice, s),
+                           "uploading batch tables");
+        if (!rc) rc = upload_items(b, s);
+        if (!rc) rc = hip_check(hipStreamSynchronize(s), "binding batch workspace");
+        return rc;
+    });
+}
+
+int sq_batch_step(sq_batch *b, double *mu, double *energies, void *stream) {
+    return guarded([&]() -> int {
+        if (!b) return fail(SQ_EINVAL, "null batch");
+        if (!b->ws) return fail(SQ_ESTATE, "call order: sq_batch_bind has not been called");
+        for (sq_ctx *c : b->ctx) {
+            int rc = check_ctx(c, kBound);
+            if (rc) return rc;
+        }
+        hipStream_t caller = static_cast<hipStream_t>(stream);
+        // the pass runs on the batch's own stream (a graph cannot be captured on
+        // the null stream), ordered after the caller's work
+        int rc = hip_check(hipEventRecord(b->ev_in, caller), "ordering the batch");
+        if (!rc) rc = hip_check(hipStreamWaitEvent(b->own, b->ev_in, 0), "ordering the batch");
+        if (!rc) rc = upload_args(b, b->own);
+        if (rc) return rc;
+        if (b->opt.use_graph) {
+            if (!b->exec) {
+                rc = hip_check(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal), "graph capture");
+                if (rc) return rc;
+                const int rc_pass = enqueue_pass(b, b->own);
+                hipGraph_t g = nullptr;
+                const int rc_end = hip_check(hipStreamEndCapture(b->own, &g), "graph capture");
+                if (rc_pass || rc_end) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc_pass ? rc_pass : rc_end;
+                }
+                b->graph = g;
+                rc = hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiation");
+                if (rc) {
+                    drop_graph(b);
+                    return rc;
+                }
+            }
+            rc = hip_check(hipGraphLaunch(b->exec, b->own), "graph launch");
+        } else {
+            rc = enqueue_pass(b, b->own);
+        }
+        if (rc) return rc;
+        rc = finish_pass(b, b->own, mu, energies);
+        const int rc2 = hip_check(hipEventRecord(b->ev_out, b->own), "ordering the batch");
+        if (!rc2) (void)hipStreamWaitEvent(caller, b->ev_out, 0);
+        return rc ? rc : rc2;
+    });
+}
+
+int sq_batch_autotune(sq_batch *b, const char *cache_path, void *stream) {
+    return guarded([&]() -> int {
+        if (!b) return fail(SQ_EINVAL, "null batch");
+        if (!b->ws) return fail(SQ_ESTATE, "call order: sq_batch_bind has not been called");
+        hipStream_t caller = static_cast<hipStream_t>(stream);
+        int rc = hip_check(hipStreamSynchronize(caller), "autotune");
+        if (rc) return rc;
+        drop_graph(b);
+        const std::string key = tune_key(b);
+        int best_block = 0, best_wg = 0;
+        if (!cache_lookup(cache_path, key, &best_block, &best_wg)) {
+            // spectral bounds of every node first (the moments need them)
+            rc = upload_args(b, b->own);
+            if (!rc) rc = enqueue_recurrences(b, true, false, b->own);
+            if (!rc) rc = hip_check(hipStreamSynchronize(b->own), "autotune bounds");
+            if (rc) return rc;
+            int max_occ = 1;
+            for (const auto &g : b->groups) max_occ = std::max(max_occ, g.occ_m);
+            std::vector<int> wgs = {1};
+            if (max_occ > 1) wgs.push_back(max_occ);
+            hipEvent_t e0, e1;
+            rc = hip_check(hipEventCreate(&e0), "autotune events");
+            if (!rc) rc = hip_check(hipEventCreate(&e1), "autotune events");
+            if (rc) return rc;
+            double best_ms = 1e300;
+            // a sample of every snapshot: its first 1/8 of the nodes
+            for (int block : {8, 32, 128}) {
+                for (int wg : wgs) {
+                    build_items(b, block, 0.125);
+                    b->wg_per_cu = wg;
+                    rc = upload_items(b, b->own);
+                    if (!rc) rc = hip_check(hipEventRecord(e0, b->own), "autotune timing");
+                    if (!rc) rc = enqueue_recurrences(b, false, true, b->own);
+                    if (!rc) rc = hip_check(hipEventRecord(e1, b->own), "autotune timing");
+                    if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune timing");
+                    float ms = 0.f;
+                    if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing");
+                    if (rc) break;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best_block = block;
+                        best_wg = wg;
+                    }
+                }
+                if (rc) break;
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (rc) return rc;
+            cache_store(cache_path, key, best_block, best_wg, best_ms);
+        }
+        b->block_nodes = best_block;
+        b->wg_per_cu = best_wg;
+        build_items(b, b->block_nodes, 1.0);
+        rc = upload_items(b, b->own);
+        if (!rc) rc = hip_check(hipStreamSynchronize(b->own), "autotune");
+        return rc;
+    });
+}
+
+int sq_batch_tiles(const sq_batch *b, int *block_nodes, int *wg_per_cu, int *n_items) {
+    if (!b) return fail(SQ_EINVAL, "null batch");
+    if (block_nodes) *block_nodes = b->block_nodes;
+    if (wg_per_cu) *wg_per_cu = b->wg_per_cu;
+    if (n_items) *n_items = int(b->items.size());
+    return SQ_OK;
+}
+
+void sq_batch_destroy(sq_batch *b) { delete b; }
 
 }  // extern "C"

@@ -30,10 +30,10 @@ namespace {
 
 constexpr int NO = kNoMax;
 
-// Rows of the cube owned by one thread: two y-adjacent columns for the large
-// regions (512-thread workgroups, 256 VGPRs per lane; the pair shares its
-// y-neighbour reads), one column for small regions.
-constexpr int rows_per_thread(int C) { return C >= 19 ? 2 : 1; }
+// Rows of the cube owned by one thread: one column for small regions, two
+// y-adjacent columns from 19 points (512-thread workgroups, 256 VGPRs per
+// lane; the pair shares its y-neighbour reads), three beyond 31 points.
+constexpr int rows_per_thread(int C) { return C > kResidentCube ? 3 : (C >= 19 ? 2 : 1); }
 
 template <int C>
 struct Shape {
@@ -48,7 +48,11 @@ struct Shape {
     static constexpr int IDLE_WRITE = ROWS * P;
     static constexpr int BLOCK = (NT + 63) / 64 * 64;
     static constexpr int NW = BLOCK / 64;
-    static constexpr int MAXRUNS = 6 * CC + 512;
+    static constexpr int MAXRUNS = (C > kResidentCube ? 4 : 6) * CC + 512;
+    // whole columns of the current vector stay in registers up to kResidentCube;
+    // wider regions stream it through the workgroup's buffers with a window of
+    // 2 NO + 2 planes in registers
+    static constexpr bool STREAM = C > kResidentCube;
     static constexpr int CPT = (CC + BLOCK - 1) / BLOCK;     // columns per thread in the set-up scan
 };
 
@@ -79,6 +83,7 @@ struct Lds {
     int ni;
     int bad;
     int nch;  // chains needed by this region (max sphere overlap depth, >= 1)
+    int item; // work-queue index taken by the workgroup
 };
 
 struct LanczosLds {
@@ -133,9 +138,19 @@ __device__ __forceinline__ double uniform(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// Butterfly sum over the 64 lanes.  The lane index is made opaque so that the
+// permute addresses are formed here rather than hoisted and kept live (they
+// would otherwise occupy registers through the whole sweep).
 __device__ __forceinline__ double wave_sum(double v) {
+    int lane = (int)__lane_id();
+    asm volatile("" : "+v"(lane));
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int off = 32; off > 0; off >>= 1) {
+        const int src = (lane ^ off) << 2;
+        const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(v));
+        const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(v));
+        v += __hiloint2double(hi, lo);
+    }
     return v;
 }
 
@@ -194,8 +209,8 @@ __device__ void sort_runs(uint2 *runs, int b, int e, bool with_chain) {
 // cube column, the clipped z-runs of their spheres split into chains of
 // disjoint runs (more than one chain only where spheres overlap).
 // ---------------------------------------------------------------------------
-template <int C, typename T, int NCH>
-__device__ void setup_region(const RecurrenceArgs &A, Lds<C, T, NCH> &L, int qi, int qj, int qk, int tid) {
+template <int C, typename T, int NCH, typename AT>
+__device__ void setup_region(const AT &A, Lds<C, T, NCH> &L, int qi, int qj, int qk, int tid) {
     using S = Shape<C>;
     const int n = A.n, m = A.m;
     if (tid == 0) {
@@ -367,6 +382,7 @@ struct Chain {
     unsigned rx;    // slot | z_first << 8 | z_last << 16 of the current record
     int vb;         // value base of the current record
     double acc;
+    double pv;      // projector value at the plane being processed (fetched one plane ahead)
 
     __device__ __forceinline__ int sl() const { return (int)(rx & 0xFFu); }
     __device__ __forceinline__ int z0() const { return (int)((rx >> 8) & 0xFFu); }
@@ -382,10 +398,11 @@ struct Chain {
         acc = 0.0;
         load(runs, sentinel);
     }
-    // projector value at plane z (0 outside the current run)
-    __device__ __forceinline__ double value(__amdgpu_buffer_rsrc_t pv, int z) const {
+    // issue the load of the projector value at plane z (0 outside the current
+    // run); it is consumed one plane later, so its latency overlaps a plane
+    __device__ __forceinline__ void fetch(__amdgpu_buffer_rsrc_t pvr, int z) {
         const bool act = (z >= z0()) & (z <= z1());
-        return bload<double>(pv, act ? (unsigned)(vb + z) * 8u : kIdleOffset, 0u);
+        pv = bload<double>(pvr, act ? (unsigned)(vb + z) * 8u : kIdleOffset, 0u);
     }
     // after plane z: a finished run adds its dot product into s[slot]
     __device__ __forceinline__ void finish(double *s, int z, const uint2 *runs, int sentinel) {
@@ -422,8 +439,10 @@ struct Cols {
     __device__ __forceinline__ bool valid(int r) const { return col[r] >= 0; }
 };
 
+// Position the chains of a column at their first records and fetch plane 0.
 template <int C, typename T, int NCH>
-__device__ __forceinline__ void chains_start(const Lds<C, T, NCH> &L, int column, Chain (&ch)[NCH]) {
+__device__ __forceinline__ void chains_start(const Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr, int column,
+                                             Chain (&ch)[NCH], int nch) {
     constexpr int SENT = Shape<C>::MAXRUNS;
     const bool ok = column >= 0;
     const int b = ok ? L.col_start[column] : 0;
@@ -433,6 +452,21 @@ __device__ __forceinline__ void chains_start(const Lds<C, T, NCH> &L, int column
         const int s0 = b + (ok ? L.col_off[column][ci] : 0);
         const int s1 = ci + 1 < NCH ? b + (ok ? L.col_off[column][ci + 1] : 0) : e;
         ch[ci].start(L.runs, s0, s1, SENT);
+        ch[ci].pv = 0.0;
+        if (ci == 0 || ci < nch) ch[ci].fetch(pvr, 0);
+    }
+}
+
+// After plane z of a column: close finished runs into s_dst and fetch plane z + 1.
+template <int C, int NCH>
+__device__ __forceinline__ void chains_advance(Chain (&ch)[NCH], double *s_dst, const uint2 *runs,
+                                               __amdgpu_buffer_rsrc_t pvr, int z, int nch) {
+#pragma unroll
+    for (int ci = 0; ci < NCH; ++ci) {
+        if (ci == 0 || ci < nch) {
+            ch[ci].finish(s_dst, z, runs, Shape<C>::MAXRUNS);
+            if (z + 1 < C) ch[ci].fetch(pvr, z + 1);
+        }
     }
 }
 
@@ -442,29 +476,28 @@ __device__ __forceinline__ void node_coords(long long q, int n, int &qi, int &qj
     qk = (int)(q / ((long long)n * n));
 }
 
-// Projector dots of the register columns tv: s[dst][I] += p_I . tv
-template <int C, typename T, int NCH, typename V>
-__device__ __forceinline__ void projector_dots(Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr,
-                                               const V (&tv)[Shape<C>::RB][C], const Cols<C> &cl, int dst,
-                                               int nch) {
-    constexpr int SENT = Shape<C>::MAXRUNS;
+// Projector dots of a vector given plane by plane: s[dst][I] += p_I . t, with
+// t(r, z) the value of the thread's column r at plane z.
+template <int C, typename T, int NCH, typename F>
+__device__ __forceinline__ void projector_dots(Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr, const Cols<C> &cl,
+                                               int dst, int nch, F &&t) {
     constexpr int RB = Shape<C>::RB;
     Chain ch[RB][NCH];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) chains_start(L, cl.col[r], ch[r]);
+    for (int r = 0; r < RB; ++r) chains_start(L, pvr, cl.col[r], ch[r], nch);
 #pragma unroll
     for (int z = 0; z < C; ++z) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const double t = (double)tv[r][z];
+            const double v = t(r, z);
 #pragma unroll
             for (int ci = 0; ci < NCH; ++ci) {
                 if (ci == 0 || ci < nch) {
-                    ch[r][ci].acc += ch[r][ci].value(pvr, z) * t;
+                    ch[r][ci].acc += ch[r][ci].pv * v;
                     pin(ch[r][ci].acc);
-                    ch[r][ci].finish(L.s[dst], z, L.runs, SENT);
                 }
             }
+            chains_advance<C, NCH>(ch[r], L.s[dst], L.runs, pvr, z, nch);
         }
     }
     __syncthreads();
@@ -523,18 +556,67 @@ __device__ __forceinline__ double stencil_sum(const PlaneView<C, T> &pv, const T
     return acc;
 }
 
+// Snapshot arguments and work items are read through the constant address
+// space: their addresses are workgroup-uniform, so the fields load into SGPRs.
+typedef __attribute__((address_space(4))) const RecurrenceArgs *SnapPtr;
+typedef __attribute__((address_space(4))) const WorkItem *ItemPtr;
+
+// The nodes a workgroup processes: one static share of snaps[0] (every node
+// q0, q0 + qs, ... < q1 of one XCD's range), or items taken from the queue
+// until it is empty.
+struct WorkSource {
+    int round = 0;
+    template <typename LdsT>
+    __device__ __forceinline__ bool next(const LaunchArgs &K, LdsT &L, int tid, SnapPtr &Ap, long long &q0,
+                                         long long &q1, long long &qs) {
+        if (!K.items) {
+            if (round++) return false;
+            Ap = (SnapPtr)K.snaps;
+            const long long nd = Ap->nd;
+            const int xcd = blockIdx.x & 7, per = gridDim.x >> 3, lw = blockIdx.x >> 3;
+            q0 = nd * xcd / 8 + lw;
+            q1 = nd * (xcd + 1) / 8;
+            qs = per;
+            return true;
+        }
+        __syncthreads();
+        if (tid == 0) L.item = atomicAdd(K.counter, 1);
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(L.item);
+        if (idx >= K.n_items) return false;
+        const ItemPtr it = (ItemPtr)K.items + idx;
+        Ap = (SnapPtr)K.snaps + it->snap;
+        q0 = it->q0;
+        q1 = it->q1;
+        qs = 1;
+        return true;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Chebyshev recurrence and moments (Sec. 3.2):
 //   t^0 = e_q, t^1 = Hhat t^0, t^{k+1} = 2 Hhat t^k - t^{k-1},
 //   rho^j = t^j[q] (j <= n_pl/2), rho^{2k} = 2 t^k.t^k - rho^0,
 //   rho^{2k-1} = 2 t^k.t^{k-1} - rho^1 (k > n_pl/4).
+// Three storage modes of the vectors (chosen by cube size and precision):
+//   FP64, resident: t^k and t^{k+1} in registers, t^{k-1} streamed through
+//     the workgroup's slot (read and overwritten by t^k plane by plane);
+//   FP32-mixed, resident: t^{k-1} also in registers, overwritten in place by
+//     t^{k+1}, so no vector moves through memory;
+//   streamed (cubes wider than kResidentCube): t^k read from buffer X with a
+//     look-ahead of NO + 1 planes, t^{k-1} read from buffer Y and replaced
+//     there by t^{k+1}; X and Y swap roles every step.
+// Global loads of plane z + 1 (potential window, t^{k-1}, projector values)
+// are issued during plane z.
 // ---------------------------------------------------------------------------
 template <int C, typename T, int NCH>
-__global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs A) {
+__global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) {
     using S = Shape<C>;
     constexpr int RB = S::RB;
     constexpr int MC = (C - 1) / 2;
-    constexpr int SENT = S::MAXRUNS;
+    constexpr bool kStream = S::STREAM;
+    constexpr bool kResident = !kStream && sizeof(T) == 4;  // t^{k-1} held in registers
+    constexpr int ZA = NO + 1;                               // look-ahead of the streamed t^k
     __shared__ Lds<C, T, NCH> L;
     const int tid = threadIdx.x;
     Cols<C> cl;
@@ -543,20 +625,27 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
 #pragma unroll
     for (int r = 0; r < RB; ++r)
         if (cl.col[r] == MC * C + MC) centre_r = r;
-    const int n = A.n;
-    const int npl = A.npl, half = npl / 2;
-    const __amdgpu_buffer_rsrc_t slr =
-        make_rsrc(reinterpret_cast<T *>(A.slots) + (long long)blockIdx.x * A.slot_elems, A.slot_elems * (long long)sizeof(T));
-    const __amdgpu_buffer_rsrc_t vr = sizeof(T) == 4 ? make_rsrc(A.veff32, A.nd * 4) : make_rsrc(A.veff, A.nd * 8);
-    const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
+    const long long slot_bytes = K.slot_elems * (long long)sizeof(T);
+    __amdgpu_buffer_rsrc_t slr =
+        make_rsrc(reinterpret_cast<T *>(K.slots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
+    __amdgpu_buffer_rsrc_t sly = slr;
+    if (kStream) sly = make_rsrc(reinterpret_cast<T *>(K.wslots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
     unsigned voff[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * (unsigned)sizeof(T) : kIdleOffset;
-    const int nwg = gridDim.x, xcd = blockIdx.x & 7, per = nwg >> 3, lw = blockIdx.x >> 3;
-    const long long qlo = A.nd * xcd / 8, qhi = A.nd * (xcd + 1) / 8;
+
+    WorkSource work;
+    SnapPtr Ap;
+    long long qfirst, qend, qstep;
+    while (work.next(K, L, tid, Ap, qfirst, qend, qstep)) {
+    const auto &A = *Ap;
+    const int n = A.n;
+    const int npl = A.npl, half = npl / 2;
+    const __amdgpu_buffer_rsrc_t vr = sizeof(T) == 4 ? make_rsrc(A.veff32, A.nd * 4) : make_rsrc(A.veff, A.nd * 8);
+    const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
     const double kin0 = -3.0 * A.w[0];
 
-    for (long long q = qlo + lw; q < qhi; q += per) {
+    for (long long q = qfirst; q < qend; q += qstep) {
         int qi, qj, qk;
         node_coords(q, n, qi, qj, qk);
         setup_region(A, L, qi, qj, qk, tid);
@@ -577,15 +666,27 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
                                         (unsigned)sizeof(T)
                                   : kIdleOffset;
         double *mrow = A.moments + q * (long long)(npl + 1);
+        auto e_q = [&](int r, int z) { return T((centre_r == r && z == MC) ? 1 : 0); };
 
-        T tv[RB][C];
+        T tv[RB][C];   // t^k (streamed mode: a window of planes)
+        T tp[RB][C];   // t^{k-1}, overwritten by t^{k+1} (FP32 resident mode only)
+        if (!kStream) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+            for (int r = 0; r < RB; ++r)
 #pragma unroll
-            for (int z = 0; z < C; ++z) tv[r][z] = T((centre_r == r && z == MC) ? 1 : 0);
+                for (int z = 0; z < C; ++z) {
+                    tv[r][z] = e_q(r, z);
+                    tp[r][z] = T(0);
+                }
+        }
         if (tid == 0) mrow[0] = 1.0;
         int cur = 0;
-        projector_dots(L, pvr, tv, cl, cur, nch);
+        // streamed mode: t^0 goes to X here, so that every sweep reads X
+        projector_dots(L, pvr, cl, cur, nch, [&](int r, int z) {
+            const T v = e_q(r, z);
+            if (kStream) bstore(v, slr, voff[r], (unsigned)(z * S::CC) * (unsigned)sizeof(T));
+            return (double)v;
+        });
 
         for (int k = 0; k < half; ++k) {
             const double al = k == 0 ? 1.0 : 2.0;
@@ -594,22 +695,46 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
                 L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur][i] : 0.0;
             Chain ch[RB][NCH];
 #pragma unroll
-            for (int r = 0; r < RB; ++r) chains_start(L, cl.col[r], ch[r]);
+            for (int r = 0; r < RB; ++r) chains_start(L, pvr, cl.col[r], ch[r], nch);
             double *snext = L.s[cur ^ 1];
             double d1 = 0.0, d2 = 0.0;
-            unsigned zb = zbase;
+            unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
             asm volatile("" : "+s"(zb));  // keep the per-plane offsets inside the step loop
+            const bool stream_prev = !kResident && k > 0;
+            // streamed t^k: the first planes of the window
+            if (kStream) {
+#pragma unroll
+                for (int z = 0; z < (ZA < C ? ZA : C); ++z)
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+                        tv[r][z] = bload<T>(slr, voff[r], (unsigned)(z * S::CC) * (unsigned)sizeof(T));
+            }
             T nv[RB][C];
+            // plane 0 loads; plane z + 1 is loaded while plane z is processed
+            double vzn[RB], tpn[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                vzn[r] = (double)bload<T>(vr, vcol[r], (unsigned)(n * n) * (zb % (unsigned)n) * (unsigned)sizeof(T));
+                tpn[r] = 0.0;
+                if (stream_prev) tpn[r] = (double)bload<T>(sly, voff[r], 0u);
+            }
 #pragma unroll
             for (int z = 0; z < C; ++z) {
                 const unsigned sz = (unsigned)(z * S::CC) * (unsigned)sizeof(T);
-                const unsigned vz_off = (unsigned)(n * n) * ((zb + (unsigned)z) % (unsigned)n) * (unsigned)sizeof(T);
                 double vz[RB], tprev[RB];
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    vz[r] = (double)bload<T>(vr, vcol[r], vz_off);
-                    tprev[r] = 0.0;
-                    if (k > 0) tprev[r] = (double)bload<T>(slr, voff[r], sz);
+                    vz[r] = vzn[r];
+                    tprev[r] = kResident ? (double)tp[r][z] : tpn[r];
+                    if (z + 1 < C) {
+                        const unsigned sz1 = (unsigned)((z + 1) * S::CC) * (unsigned)sizeof(T);
+                        const unsigned vz1 = (unsigned)(n * n) * ((zb + (unsigned)(z + 1)) % (unsigned)n) *
+                                             (unsigned)sizeof(T);
+                        vzn[r] = (double)bload<T>(vr, vcol[r], vz1);
+                        if (stream_prev) tpn[r] = (double)bload<T>(sly, voff[r], sz1);
+                    }
+                    if (kStream && z + ZA < C)
+                        tv[r][z + ZA] = bload<T>(slr, voff[r], (unsigned)((z + ZA) * S::CC) * (unsigned)sizeof(T));
                     L.plane[z & 1][cl.pcw[r]] = tv[r][z];
                 }
                 __syncthreads();
@@ -627,18 +752,24 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
                     for (int ci = 0; ci < NCH; ++ci) {
                         pval[ci] = 0.0;
                         if (ci == 0 || ci < nch) {
-                            pval[ci] = ch[r][ci].value(pvr, z);
+                            pval[ci] = ch[r][ci].pv;
                             nvd += L.cs[ch[r][ci].sl()] * pval[ci];
                         }
                     }
-                    // a column past the cube edge (odd C) shares its neighbour reads
-                    // with a real column; it must stay zero, since it is that
-                    // column's y + 1 neighbour
+                    // a column past the cube edge shares its neighbour reads with
+                    // a real column; it must stay zero, since it is that column's
+                    // y neighbour
                     if (!cl.valid(r)) nvd = 0.0;
                     const T nvt = T(nvd);
                     nvd = (double)nvt;
-                    nv[r][z] = nvt;
-                    bstore(tv[r][z], slr, voff[r], sz);
+                    if (kResident) {
+                        tp[r][z] = nvt;
+                    } else if (kStream) {
+                        bstore(nvt, sly, voff[r], sz);  // t^{k+1} over t^{k-1}
+                    } else {
+                        nv[r][z] = nvt;
+                        bstore(tv[r][z], slr, voff[r], sz);
+                    }
                     d1 += nvd * nvd;
                     d2 += nvd * tz;
                     pin(d1);
@@ -648,9 +779,9 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
                         if (ci == 0 || ci < nch) {
                             ch[r][ci].acc += pval[ci] * nvd;
                             pin(ch[r][ci].acc);
-                            ch[r][ci].finish(snext, z, L.runs, SENT);
                         }
                     }
+                    chains_advance<C, NCH>(ch[r], snext, L.runs, pvr, z, nch);
                     if (z == MC && centre_r == r) {
                         mrow[k + 1] = nvd;
                         if (k == 0) L.bc[2] = nvd;
@@ -671,14 +802,30 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(RecurrenceArgs
                         atomicOr(A.flags, kFlagBounds);
                 }
             }
+            // t^k -> t^{k-1}, t^{k+1} -> t^k
+            if (kStream) {
+                const __amdgpu_buffer_rsrc_t t = slr;
+                slr = sly;
+                sly = t;
+            } else {
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
+                for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int z = 0; z < C; ++z) tv[r][z] = nv[r][z];
+                    for (int z = 0; z < C; ++z) {
+                        if (kResident) {
+                            const T t = tv[r][z];
+                            tv[r][z] = tp[r][z];
+                            tp[r][z] = t;
+                        } else {
+                            tv[r][z] = nv[r][z];
+                        }
+                    }
+            }
             for (int i = tid; i < kMaxImages; i += S::BLOCK) L.s[cur][i] = 0.0;
             cur ^= 1;
             __syncthreads();
         }
+    }
     }
 }
 
@@ -718,40 +865,55 @@ __device__ double sturm_bisect(int k, const double *a, const double *b, int targ
     return hi;
 }
 
+// Resident cubes keep v_j in registers; the sweep writes v_j to the slot (it
+// is v_{j-1} of the next step) and u to wslot, and the second pass rebuilds
+// w = u - alpha v_j in the registers.  Streamed cubes keep w_j (not yet
+// divided by beta_j) in buffer X and v_{j-1} (as stored w_{j-1}) in buffer Y,
+// read with a look-ahead window and scaled on load; the second pass writes w
+// over Y and the two buffers swap roles.
 template <int C, int NCH>
-__global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs A) {
+__global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) {
     using S = Shape<C>;
     using T = double;
     constexpr int RB = S::RB;
-    constexpr int SENT = S::MAXRUNS;
+    constexpr bool kStream = S::STREAM;
+    constexpr int ZA = NO + 1;
     __shared__ Lds<C, T, NCH> L;
     __shared__ LanczosLds LL;
     const int tid = threadIdx.x;
     Cols<C> cl;
     cl.init(tid);
-    const int n = A.n;
-    // slot: v_{j-1}, overwritten by v_j during the sweep; wslot: u = H v_j - beta v_{j-1}
-    const __amdgpu_buffer_rsrc_t slr =
-        make_rsrc(reinterpret_cast<T *>(A.slots) + (long long)blockIdx.x * A.slot_elems, A.slot_elems * 8);
+    const long long slot_bytes = K.slot_elems * 8;
+    // resident: slr holds v_{j-1}, overwritten by v_j during the sweep.
+    // streamed: slr = X (current), sly = Y (previous).  wlr: u = H v_j - beta v_{j-1}
+    __amdgpu_buffer_rsrc_t slr =
+        make_rsrc(reinterpret_cast<T *>(K.slots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
     const __amdgpu_buffer_rsrc_t wlr =
-        make_rsrc(reinterpret_cast<T *>(A.wslots) + (long long)blockIdx.x * A.slot_elems, A.slot_elems * 8);
-    const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
-    const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
+        make_rsrc(reinterpret_cast<T *>(K.wslots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
+    __amdgpu_buffer_rsrc_t sly = slr;
+    if (kStream) sly = make_rsrc(reinterpret_cast<T *>(K.xslots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
     unsigned voff[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * 8u : kIdleOffset;
-    const int nwg = gridDim.x, xcd = blockIdx.x & 7, per = nwg >> 3, lw = blockIdx.x >> 3;
-    const long long qlo = A.nd * xcd / 8, qhi = A.nd * (xcd + 1) / 8;
+    const long long ns = (long long)C * C * C;
+
+    WorkSource work;
+    SnapPtr Ap;
+    long long qfirst, qend, qstep;
+    while (work.next(K, L, tid, Ap, qfirst, qend, qstep)) {
+    const auto &A = *Ap;
+    const int n = A.n;
+    const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
+    const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
     const double kin0 = -3.0 * A.w[0];
     double kw[NO + 1];
     kw[0] = 0.0;
 #pragma unroll
     for (int d = 1; d <= NO; ++d) kw[d] = -0.5 * A.w[d];
-    const long long ns = (long long)C * C * C;
     const int kmax = (long long)A.n_lanczos < ns ? A.n_lanczos : (int)ns;
     const double rnorm = 1.0 / A.start_norm;
 
-    for (long long q = qlo + lw; q < qhi; q += per) {
+    for (long long q = qfirst; q < qend; q += qstep) {
         int qi, qj, qk;
         node_coords(q, n, qi, qj, qk);
         setup_region(A, L, qi, qj, qk, tid);
@@ -763,39 +925,72 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
         for (int r = 0; r < RB; ++r)
             vcol[r] = cl.valid(r) ? (unsigned)(pmod(qi - A.m + cl.x, n) + n * pmod(qj - A.m + cl.y0 + r, n)) * 8u
                                   : kIdleOffset;
+        // v_1[a] = (u(a) - 1/2) / |u - 1/2|, a = local cube index
+        auto start = [&](int r, int z) {
+            return cl.valid(r) ? (unit_from_seed((unsigned long long)(cl.col[r] + C * C * z)) - 0.5) * rnorm : 0.0;
+        };
 
-        double tv[RB][C];
+        double tv[RB][C];  // v_j (streamed mode: a window of planes)
+        if (!kStream) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+            for (int r = 0; r < RB; ++r)
 #pragma unroll
-            for (int z = 0; z < C; ++z)
-                tv[r][z] = cl.valid(r) ? (unit_from_seed((unsigned long long)(cl.col[r] + C * C * z)) - 0.5) * rnorm
-                                       : 0.0;
+                for (int z = 0; z < C; ++z) tv[r][z] = start(r, z);
+        }
         int cur = 0;
-        projector_dots(L, pvr, tv, cl, cur, nch);
+        // streamed mode: v_1 goes to X here, so that every sweep reads X
+        projector_dots(L, pvr, cl, cur, nch, [&](int r, int z) {
+            if (!kStream) return tv[r][z];
+            const double v = start(r, z);
+            bstore(v, slr, voff[r], (unsigned)(z * S::CC) * 8u);
+            return v;
+        });
 
         double bprev = 0.0, gersh = 0.0;
+        // v_j = scx * (register columns, or X when streamed), v_{j-1} = scy * slot
+        // (or Y): the vectors are kept as w = u - alpha v, not divided by beta
+        double scx = 1.0, scy = 0.0;
         int ksteps = kmax;
         for (int j = 0; j < kmax; ++j) {
-            // w = H v - beta_{j-1} v_{j-1};  slot <- v;  alpha = w . v
+            // Local part of u = H v_j - beta_{j-1} v_{j-1} (stencil and potential)
+            // -> wslot.  The projector part, sum_I c_I (p_I . v_j) p_I, is added
+            // in the second pass, where the same walk over the projector runs
+            // also forms p . w; its contribution to alpha is sum_I c_I (p_I . v_j)^2.
             for (int i = tid; i < kMaxImages; i += S::BLOCK)
                 L.cs[i] = i < ni ? L.img_coef[i] * L.s[cur][i] : 0.0;
-            Chain ch[RB][NCH];
-#pragma unroll
-            for (int r = 0; r < RB; ++r) chains_start(L, cl.col[r], ch[r]);
-            unsigned zb = zbase;
+            unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
             asm volatile("" : "+s"(zb));
+            const __amdgpu_buffer_rsrc_t prev = kStream ? sly : slr;
+            const double sprev = scy;
+            if (kStream) {
+#pragma unroll
+                for (int z = 0; z < (ZA < C ? ZA : C); ++z)
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) tv[r][z] = bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u);
+            }
             double da = 0.0;
+            double vzn[RB], vpn[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * (zb % (unsigned)n) * 8u);
+                vpn[r] = 0.0;
+                if (j > 0) vpn[r] = sprev * bload<double>(prev, voff[r], 0u);
+            }
 #pragma unroll
             for (int z = 0; z < C; ++z) {
                 const unsigned sz = (unsigned)(z * S::CC) * 8u;
-                const unsigned vz_off = (unsigned)(n * n) * ((zb + (unsigned)z) % (unsigned)n) * 8u;
                 double vz[RB], vprev[RB];
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    vz[r] = bload<double>(vr, vcol[r], vz_off);
-                    vprev[r] = 0.0;
-                    if (j > 0) vprev[r] = bload<double>(slr, voff[r], sz);
+                    vz[r] = vzn[r];
+                    vprev[r] = vpn[r];
+                    if (z + 1 < C) {
+                        const unsigned sz1 = (unsigned)((z + 1) * S::CC) * 8u;
+                        vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)(z + 1)) % (unsigned)n) * 8u);
+                        if (j > 0) vpn[r] = sprev * bload<double>(prev, voff[r], sz1);
+                    }
+                    if (kStream && z + ZA < C)
+                        tv[r][z + ZA] = bload<double>(slr, voff[r], (unsigned)((z + ZA) * S::CC) * 8u);
                     L.plane[z & 1][cl.pcw[r]] = tv[r][z];
                 }
                 __syncthreads();
@@ -804,57 +999,71 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
                 load_yrows<C, double>(pv, tv, z, yrow);
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    double u = stencil_sum<C, double>(pv, yrow, tv[r], r, z, kw) + (vz[r] + kin0) * tv[r][z];
-                    double pval[NCH];
-#pragma unroll
-                    for (int ci = 0; ci < NCH; ++ci) {
-                        pval[ci] = 0.0;
-                        if (ci == 0 || ci < nch) {
-                            pval[ci] = ch[r][ci].value(pvr, z);
-                            u += L.cs[ch[r][ci].sl()] * pval[ci];
-                        }
-                    }
+                    double u = scx * (stencil_sum<C, double>(pv, yrow, tv[r], r, z, kw) + (vz[r] + kin0) * tv[r][z]);
                     u -= bprev * vprev[r];
                     if (!cl.valid(r)) u = 0.0;  // column past the cube edge stays zero
-                    bstore(tv[r][z], slr, voff[r], sz);
+                    if (!kStream) bstore(tv[r][z], slr, voff[r], sz);
                     bstore(u, wlr, voff[r], sz);
                     da += u * tv[r][z];
                     pin(da);
-#pragma unroll
-                    for (int ci = 0; ci < NCH; ++ci)
-                        if (ci == 0 || ci < nch) ch[r][ci].finish(L.s[cur ^ 1], z, L.runs, SENT);  // advance
                 }
             }
             __syncthreads();
+            double dimg = 0.0;
+            for (int i = tid; i < ni; i += S::BLOCK) dimg += L.cs[i] * L.s[cur][i];
+            block_sum2(L, da, dimg, tid);
+            const double alpha = uniform(scx * da + dimg);
             double dummy = 0.0;
-            block_sum2(L, da, dummy, tid);
-            const double alpha = da;
 
-            // w = u - alpha v (into the register columns);  beta = |w|;  p . w
-            // (taken from w itself: a projector dot carried by linearity,
-            // (p.u - alpha p.v) / beta, grows its rounding error by |alpha/beta|
-            // per step)
+            // w = u - alpha v_j with the projector part of u added here;
+            // beta = |w|;  p . w (taken from w itself: a projector dot carried
+            // by linearity, (p.u - alpha p.v) / beta, grows its rounding error by
+            // |alpha/beta| per step).  Loads of planes z + 1 and z + 2 are in
+            // flight while plane z is processed.
             double db = 0.0;
+            Chain ch[RB][NCH];
 #pragma unroll
-            for (int r = 0; r < RB; ++r) chains_start(L, cl.col[r], ch[r]);
+            for (int r = 0; r < RB; ++r) chains_start(L, pvr, cl.col[r], ch[r], nch);
+            double un[2][RB], xn[2][RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+#pragma unroll
+                for (int z = 0; z < 2; ++z) {
+                    un[z][r] = z < C ? bload<double>(wlr, voff[r], (unsigned)(z * S::CC) * 8u) : 0.0;
+                    xn[z][r] = 0.0;
+                    if (kStream && z < C) xn[z][r] = bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u);
+                }
+            }
 #pragma unroll
             for (int z = 0; z < C; ++z) {
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    const unsigned sz = (unsigned)(z * S::CC) * 8u;
-                    const double w = bload<double>(wlr, voff[r], sz) - alpha * bload<double>(slr, voff[r], sz);
-                    tv[r][z] = w;
+                    double uz = un[z & 1][r];
+                    const double vj = scx * (kStream ? xn[z & 1][r] : tv[r][z]);
+                    if (z + 2 < C) {
+                        const unsigned sz2 = (unsigned)((z + 2) * S::CC) * 8u;
+                        un[z & 1][r] = bload<double>(wlr, voff[r], sz2);
+                        if (kStream) xn[z & 1][r] = bload<double>(slr, voff[r], sz2);
+                    }
+#pragma unroll
+                    for (int ci = 0; ci < NCH; ++ci)
+                        if (ci == 0 || ci < nch) uz += L.cs[ch[r][ci].sl()] * ch[r][ci].pv;
+                    double w = uz - alpha * vj;
+                    if (!cl.valid(r)) w = 0.0;
+                    if (kStream) bstore(w, sly, voff[r], (unsigned)(z * S::CC) * 8u);
+                    else tv[r][z] = w;
                     db += w * w;
                     pin(db);
 #pragma unroll
                     for (int ci = 0; ci < NCH; ++ci) {
                         if (ci == 0 || ci < nch) {
-                            ch[r][ci].acc += ch[r][ci].value(pvr, z) * w;
+                            ch[r][ci].acc += ch[r][ci].pv * w;
                             pin(ch[r][ci].acc);
-                            ch[r][ci].finish(L.s[cur ^ 1], z, L.runs, SENT);
                         }
                     }
+                    chains_advance<C, NCH>(ch[r], L.s[cur ^ 1], L.runs, pvr, z, nch);
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
             __syncthreads();
             block_sum2(L, db, dummy, tid);
@@ -870,10 +1079,14 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
                 break;
             }
             const double rb = uniform(1.0 / beta);
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-#pragma unroll
-                for (int z = 0; z < C; ++z) tv[r][z] *= rb;
+            if (kStream) {
+                // X <- w_j, Y <- the buffer holding v_j
+                const __amdgpu_buffer_rsrc_t t = slr;
+                slr = sly;
+                sly = t;
+            }
+            scy = scx;
+            scx = rb;
             for (int i = tid; i < kMaxImages; i += S::BLOCK) {
                 L.s[cur ^ 1][i] = L.s[cur ^ 1][i] * rb;
                 L.s[cur][i] = 0.0;
@@ -893,6 +1106,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(RecurrenceArgs
             A.zeta[q] = (1.0 + A.margin) * 0.5 * (lmx - lmn);
         }
         __syncthreads();
+    }
     }
 }
 
@@ -917,6 +1131,12 @@ __global__ void to_fp32_kernel(const double *src, float *dst, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
         dst[i] = (float)src[i];
+}
+
+// Fill of int counters (a kernel, not a memset, so that it can sit in a
+// captured graph).
+__global__ void zero_ints_kernel(int *p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 __global__ void weights_kernel(const double *mom, const double *ctab, double *W, long long nd, int npl) {
@@ -1015,11 +1235,58 @@ __global__ __launch_bounds__(kRedBlock) void count_kernel(const double *W, const
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// N(mu_eval) of every snapshot whose Brent search is pending (blockIdx.y =
+// snapshot); per snapshot the same partial sums as count_kernel.
+__global__ __launch_bounds__(kRedBlock) void count_batch_kernel(const FermiSnap *fs, const BrentState *st,
+                                                                double *partials) {
+    __shared__ double sh[kRedBlock / 64];
+    const int si = blockIdx.y;
+    const int ph = st[si].phase;
+    if (ph < kBrentLow || ph > kBrentIterate) return;
+    const FermiSnap f = fs[si];
+    const double mu = st[si].mu_eval;
+    const long long total = f.nd * f.nq;
+    double acc = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long q = i / f.nq;
+        const int k = (int)(i - q * f.nq);
+        const double lam = f.zeta[q] * f.rk[k] + f.chi[q];
+        acc += fermi_fn((lam - mu) / f.kT) * f.W[i];
+    }
+    const double s = block_reduce(acc, sh);
+    if (threadIdx.x == 0) partials[(long long)si * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void brent_begin_kernel(BrentState *st, const BrentParams *prm, const double *ext, int nsnap) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsnap) return;
+    const BrentParams p = prm[i];
+    BrentState b;
+    brent_begin(b, ext[2 * i], ext[2 * i + 1], p.kT, p.n_e, p.xtol, p.ftol, p.max_it);
+    st[i] = b;
+}
+
+// One Brent step per snapshot from the fixed-order sum of its partials
+// (N = 2 sum_q sum_k g(lambda_qk) W_qk).
+__global__ void brent_feed_kernel(BrentState *st, const double *partials, int nblk, int nsnap) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsnap) return;
+    BrentState b = st[i];
+    if (b.phase < kBrentLow || b.phase > kBrentIterate) return;
+    double sum = 0.0;
+    for (int j = 0; j < nblk; ++j) sum += partials[(long long)i * nblk + j];
+    brent_feed(b, 2.0 * sum);  // two electrons per state
+    st[i] = b;
+}
+
 __global__ __launch_bounds__(kRedBlock) void density_kernel(const double *W, const double *chi,
                                                             const double *zeta, const double *rk,
-                                                            long long nd, int nq, double mu, double kT,
-                                                            double h3, double *rho, double *partials) {
+                                                            long long nd, int nq, double mu_arg,
+                                                            const double *mu_dev, double kT, double h3,
+                                                            double *rho, double *partials) {
     __shared__ double sh[kRedBlock / 64];
+    const double mu = mu_dev ? *mu_dev : mu_arg;
     double eb = 0.0, en = 0.0, er = 0.0;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nd;
          q += (long long)gridDim.x * blockDim.x) {
@@ -1064,35 +1331,66 @@ __global__ void sum_partials(const double *partials, int nblk, int width, double
 
 }  // namespace
 
-#define SQ_ALL_CUBES X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29) X(31)
+#define SQ_ALL_CUBES X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29) X(31) X(33) X(35) X(37)
 
 #ifndef SQ_COMMON_ONLY
+// Launch helpers.  Streamed cubes (wider than kResidentCube) are built with
+// two projector chains only; the host rejects deeper sphere overlaps there.
+template <int c>
+hipError_t launch_lanczos_t(const LaunchArgs &a, int nch, int nwg, hipStream_t s) {
+    if constexpr (!Shape<c>::STREAM) {
+        if (nch > 2) {
+            hipLaunchKernelGGL((lanczos_kernel<c, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            return hipGetLastError();
+        }
+    } else if (nch > 2) {
+        return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((lanczos_kernel<c, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+template <int c>
+hipError_t launch_moments_t(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s) {
+    if constexpr (!Shape<c>::STREAM) {
+        if (nch > 2) {
+            if (mixed) hipLaunchKernelGGL((moments_kernel<c, float, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            else hipLaunchKernelGGL((moments_kernel<c, double, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            return hipGetLastError();
+        }
+    } else if (nch > 2) {
+        return hipErrorInvalidValue;
+    }
+    if (mixed) hipLaunchKernelGGL((moments_kernel<c, float, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((moments_kernel<c, double, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+template <int c>
+hipError_t occupancy_t(bool lanczos, bool mixed, int nch, int *nb) {
+    const int B = Shape<c>::BLOCK;
+    if constexpr (!Shape<c>::STREAM) {
+        if (nch > 2) {
+            if (lanczos) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, 4>, B, 0);
+            if (mixed) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float, 4>, B, 0);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double, 4>, B, 0);
+        }
+    } else if (nch > 2) {
+        return hipErrorInvalidValue;
+    }
+    if (lanczos) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, 2>, B, 0);
+    if (mixed) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float, 2>, B, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double, 2>, B, 0);
+}
+
 // Per-cube entry points of this translation unit (SQ_CUBES lists its cubes).
 #define X(c)                                                                                        \
-    hipError_t lanczos_c##c(const RecurrenceArgs &a, int nwg, hipStream_t s) {                      \
-        if (a.nch > 2) hipLaunchKernelGGL((lanczos_kernel<c, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
-        else hipLaunchKernelGGL((lanczos_kernel<c, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);       \
-        return hipGetLastError();                                                                   \
+    hipError_t lanczos_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s) {                 \
+        return launch_lanczos_t<c>(a, nch, nwg, s);                                                 \
     }                                                                                               \
-    hipError_t moments_c##c(const RecurrenceArgs &a, bool mixed, int nwg, hipStream_t s) {          \
-        if (a.nch > 2) {                                                                            \
-            if (mixed) hipLaunchKernelGGL((moments_kernel<c, float, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
-            else hipLaunchKernelGGL((moments_kernel<c, double, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
-        } else {                                                                                    \
-            if (mixed) hipLaunchKernelGGL((moments_kernel<c, float, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
-            else hipLaunchKernelGGL((moments_kernel<c, double, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a); \
-        }                                                                                           \
-        return hipGetLastError();                                                                   \
+    hipError_t moments_c##c(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s) {     \
+        return launch_moments_t<c>(a, nch, mixed, nwg, s);                                          \
     }                                                                                               \
     hipError_t occupancy_c##c(bool lanczos, bool mixed, int nch, int *nb) {                         \
-        if (lanczos)                                                                                \
-            return nch > 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, 4>, Shape<c>::BLOCK, 0) \
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, 2>, Shape<c>::BLOCK, 0); \
-        if (mixed)                                                                                  \
-            return nch > 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float, 4>, Shape<c>::BLOCK, 0) \
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float, 2>, Shape<c>::BLOCK, 0); \
-        return nch > 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double, 4>, Shape<c>::BLOCK, 0) \
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double, 2>, Shape<c>::BLOCK, 0); \
+        return occupancy_t<c>(lanczos, mixed, nch, nb);                                             \
     }                                                                                               \
     int block_c##c() { return Shape<c>::BLOCK; }
 #ifdef SQ_CUBES
@@ -1105,8 +1403,8 @@ SQ_ALL_CUBES
 
 #if defined(SQ_COMMON_ONLY) || !defined(SQ_CUBES)
 #define X(c)                                                                         \
-    hipError_t lanczos_c##c(const RecurrenceArgs &a, int nwg, hipStream_t s);       \
-    hipError_t moments_c##c(const RecurrenceArgs &a, bool mixed, int nwg, hipStream_t s); \
+    hipError_t lanczos_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s);  \
+    hipError_t moments_c##c(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s); \
     hipError_t occupancy_c##c(bool lanczos, bool mixed, int nch, int *nb);          \
     int block_c##c();
 SQ_ALL_CUBES
@@ -1130,18 +1428,18 @@ hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int nch, int *b
     }
 }
 
-hipError_t launch_lanczos(const RecurrenceArgs &a, int nwg, hipStream_t s) {
-    switch (a.C) {
-#define X(c) case c: return lanczos_c##c(a, nwg, s);
+hipError_t launch_lanczos(const LaunchArgs &a, int C, int nch, int nwg, hipStream_t s) {
+    switch (C) {
+#define X(c) case c: return lanczos_c##c(a, nch, nwg, s);
         SQ_ALL_CUBES
 #undef X
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_moments(const RecurrenceArgs &a, bool mixed, int nwg, hipStream_t s) {
-    switch (a.C) {
-#define X(c) case c: return moments_c##c(a, mixed, nwg, s);
+hipError_t launch_moments(const LaunchArgs &a, int C, int nch, bool mixed, int nwg, hipStream_t s) {
+    switch (C) {
+#define X(c) case c: return moments_c##c(a, nch, mixed, nwg, s);
         SQ_ALL_CUBES
 #undef X
         default: return hipErrorInvalidValue;
@@ -1162,6 +1460,11 @@ hipError_t launch_set_bounds(const double *lmin, const double *lmax, double *chi
                              long long nd, double margin, hipStream_t s) {
     hipLaunchKernelGGL(set_bounds_kernel, dim3(grid_for(nd, 256)), dim3(256), 0, s, lmin, lmax, chi, zeta,
                        nd, margin);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 
@@ -1194,11 +1497,27 @@ hipError_t launch_count(const double *W, const double *chi, const double *zeta, 
 }
 
 hipError_t launch_density(const double *W, const double *chi, const double *zeta, const double *rk,
-                          long long nd, int nq, double mu, double kT, double h3, double *rho,
-                          double *partials, int nblk, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(density_kernel, dim3(nblk), dim3(kRedBlock), 0, s, W, chi, zeta, rk, nd, nq, mu, kT,
-                       h3, rho, partials);
+                          long long nd, int nq, double mu, const double *mu_dev, double kT, double h3,
+                          double *rho, double *partials, int nblk, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(density_kernel, dim3(nblk), dim3(kRedBlock), 0, s, W, chi, zeta, rk, nd, nq, mu, mu_dev,
+                       kT, h3, rho, partials);
     hipLaunchKernelGGL(sum_partials, dim3(1), dim3(64), 0, s, partials, nblk, 3, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_brent_begin(BrentState *st, const BrentParams *prm, const double *ext, int nsnap, hipStream_t s) {
+    hipLaunchKernelGGL(brent_begin_kernel, dim3((nsnap + 63) / 64), dim3(64), 0, s, st, prm, ext, nsnap);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_batch(const FermiSnap *fs, const BrentState *st, int nsnap, double *partials, int nblk,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(count_batch_kernel, dim3(nblk, nsnap), dim3(kRedBlock), 0, s, fs, st, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_brent_feed(BrentState *st, const double *partials, int nblk, int nsnap, hipStream_t s) {
+    hipLaunchKernelGGL(brent_feed_kernel, dim3((nsnap + 63) / 64), dim3(64), 0, s, st, partials, nblk, nsnap);
     return hipGetLastError();
 }
 

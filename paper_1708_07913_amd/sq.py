@@ -34,6 +34,10 @@ class Options(ct.Structure):
                 ("workgroups", ct.c_int)]
 
 
+class BatchOptions(ct.Structure):
+    _fields_ = [("block_nodes", ct.c_int), ("wg_per_cu", ct.c_int), ("use_graph", ct.c_int)]
+
+
 _lib = None
 
 
@@ -62,8 +66,21 @@ def load_library():
     lib.sq_density_energy.argtypes = [P, P, D, P, dp, P]
     lib.sq_destroy.argtypes = [P]
     lib.sq_destroy.restype = None
+    lib.sq_batch_default_options.argtypes = [ct.POINTER(BatchOptions)]
+    lib.sq_batch_default_options.restype = None
+    lib.sq_batch_create.argtypes = [ct.POINTER(P), ct.POINTER(P), I, ct.POINTER(P), ct.POINTER(P), dp,
+                                    ct.POINTER(BatchOptions)]
+    lib.sq_batch_query.argtypes = [P, ct.POINTER(S)]
+    lib.sq_batch_bind.argtypes = [P, P, S, P]
+    lib.sq_batch_step.argtypes = [P, dp, dp, P]
+    lib.sq_batch_autotune.argtypes = [P, ct.c_char_p, P]
+    lib.sq_batch_tiles.argtypes = [P, ct.POINTER(I), ct.POINTER(I), ct.POINTER(I)]
+    lib.sq_batch_destroy.argtypes = [P]
+    lib.sq_batch_destroy.restype = None
     for name in ("sq_setup", "sq_query", "sq_bind", "sq_update_veff", "sq_spectral_bounds",
-                 "sq_set_bounds", "sq_moments", "sq_fermi_level", "sq_density_energy"):
+                 "sq_set_bounds", "sq_moments", "sq_fermi_level", "sq_density_energy",
+                 "sq_batch_create", "sq_batch_query", "sq_batch_bind", "sq_batch_step",
+                 "sq_batch_autotune", "sq_batch_tiles"):
         getattr(lib, name).restype = ct.c_int
     _lib = lib
     return lib
@@ -201,3 +218,65 @@ class SQ:
         mu = self.fermi_level(mom, n_electrons)
         rho, e = self.density_energy(mom, mu)
         return mom, mu, rho, e
+
+
+class Batch:
+    """Many snapshots (bound SQ objects of one precision) advanced together:
+    one call runs bounds, moments, Fermi level, density and energies of all
+    of them (persistent work-queue launches; optionally one hipGraph)."""
+
+    def __init__(self, snaps, n_electrons, block_nodes=0, wg_per_cu=0, use_graph=True, stream=None):
+        import torch
+        lib = load_library()
+        self.torch = torch
+        self.snaps = list(snaps)
+        n = len(self.snaps)
+        self.n_electrons = np.ascontiguousarray(np.asarray(n_electrons, dtype=np.float64).reshape(n))
+        dev = self.snaps[0].device
+        self.moments = [torch.empty((s.nd, s.npl + 1), dtype=torch.float64, device=dev) for s in self.snaps]
+        self.rho = [torch.empty(s.nd, dtype=torch.float64, device=dev) for s in self.snaps]
+        opt = BatchOptions()
+        lib.sq_batch_default_options(ct.byref(opt))
+        opt.block_nodes, opt.wg_per_cu, opt.use_graph = int(block_nodes), int(wg_per_cu), int(bool(use_graph))
+        ctxs = (ct.c_void_p * n)(*[s._ctx for s in self.snaps])
+        mom = (ct.c_void_p * n)(*[t.data_ptr() for t in self.moments])
+        rho = (ct.c_void_p * n)(*[t.data_ptr() for t in self.rho])
+        b = ct.c_void_p()
+        dp = ct.POINTER(ct.c_double)
+        _check(lib.sq_batch_create(ct.byref(b), ctxs, n, mom, rho, self.n_electrons.ctypes.data_as(dp),
+                                   ct.byref(opt)))
+        self._b = b
+        self._stream = stream
+        ws = ct.c_size_t()
+        _check(lib.sq_batch_query(b, ct.byref(ws)))
+        self.workspace_bytes = ws.value
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        self._ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        _check(lib.sq_batch_bind(b, self._ws_ptr, self.workspace_bytes, self._stream_ptr()))
+
+    def _stream_ptr(self):
+        s = self._stream if self._stream is not None else self.torch.cuda.current_stream()
+        return s.cuda_stream
+
+    def step(self):
+        """One pass of every snapshot; returns (mu[n], energies[n, 4])."""
+        n = len(self.snaps)
+        mu = np.zeros(n)
+        e = np.zeros((n, 4))
+        dp = ct.POINTER(ct.c_double)
+        _check(_lib.sq_batch_step(self._b, mu.ctypes.data_as(dp), e.ctypes.data_as(dp), self._stream_ptr()))
+        return mu, e
+
+    def autotune(self, cache_path=None):
+        _check(_lib.sq_batch_autotune(self._b, cache_path.encode() if cache_path else None, self._stream_ptr()))
+        return self.tiles()
+
+    def tiles(self):
+        b, w, k = ct.c_int(), ct.c_int(), ct.c_int()
+        _check(_lib.sq_batch_tiles(self._b, ct.byref(b), ct.byref(w), ct.byref(k)))
+        return {"block_nodes": b.value, "wg_per_cu": w.value, "n_items": k.value}
+
+    def __del__(self):
+        if getattr(self, "_b", None) and _lib is not None:
+            _lib.sq_batch_destroy(self._b)
+            self._b = None

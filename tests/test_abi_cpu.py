@@ -63,7 +63,7 @@ def _setup(**over):
     (dict(npl=0), "npl"),
     (dict(kT=0.0), "kT"),
     (dict(rcut=0.2), "m >= 1"),
-    (dict(rcut=9.0), "wider than 31"),
+    (dict(rcut=9.5), "wider than 37"),
     (dict(natom=-1), "natom"),
     (dict(xyz=None), "atom_xyz"),
     (dict(kb=np.array([[0.0, 2.5, 0.5]])), "projector"),
@@ -74,6 +74,18 @@ def test_setup_rejects_invalid_arguments(over, fragment):
     rc, msg = _setup(**over)
     assert rc == -1, (rc, msg)
     assert fragment in msg
+
+
+def test_streamed_regions_reject_deep_projector_overlap():
+    # three coincident spheres: depth 3 is served by four chains on resident
+    # cubes, but streamed cubes (wider than 31 points) carry two
+    xyz = np.array([[1.0, 2.0, 3.0]] * 3)
+    kb = np.array([[0.7, 2.5, 0.5]] * 3)
+    rc, msg = _setup(natom=3, xyz=xyz, kb=kb, rcut=8.0)
+    assert rc == -7, (rc, msg)
+    assert "two overlapping" in msg
+    rc, msg = _setup(natom=3, xyz=xyz, kb=kb, rcut=7.5)
+    assert rc != -7, (rc, msg)  # without a GPU, set-up stops later (SQ_EDEVICE)
 
 
 def test_setup_rejects_bad_options():

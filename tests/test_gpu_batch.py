@@ -1,0 +1,172 @@
+"""Batched snapshots on the GPU: one pass of many snapshots (persistent
+work-queue launches per cube size, device-side Brent, hipGraph replay)
+against the single-snapshot path and the FP64 oracle, through the C ABI."""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_07913_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_07913_amd import sq
+    sq.load_library()
+    torch.cuda.set_device(0)
+
+
+def _sq():
+    from paper_1708_07913_amd import sq
+    return sq
+
+
+def _small_ensemble(precision="fp64"):
+    """Four uneven snapshots: three cube sizes (one streamed), three n_pl."""
+    return [
+        W.fcc_workload("b0_al4_c11", 1, 8.0, 0.1, 21, 0.5, 2.5, 24, 1.0, precision=precision),
+        W.fcc_workload("b1_al4_c15", 1, 8.0, 0.15, 22, 0.5, 3.5, 16, 3.0, precision=precision),
+        W.fcc_workload("b2_al32_c11", 2, 7.78, 0.2, 23, 0.5, 2.5, 32, 1.0, precision=precision),
+        W.fcc_workload("b3_al4_c33", 1, 8.0, 0.1, 24, 0.5, 8.0, 16, 1.0, precision=precision),
+    ]
+
+
+def _snaps(wls):
+    sq = _sq()
+    return [sq.SQ.from_workload(wl, veff=torch.from_numpy(wl.veff()).cuda()) for wl in wls]
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _single(snaps, wls):
+    out = []
+    for g, wl in zip(snaps, wls):
+        mom, mu, rho, e = g.scf_pass(wl.n_electrons)
+        out.append((_np(mom), mu, _np(rho), e))
+    return out
+
+
+def _compare(batch, mu, e, ref, wls, tol_rho=1e-12):
+    for i, (wl, (mom1, mu1, rho1, e1)) in enumerate(zip(wls, ref)):
+        m = _np(batch.moments[i])
+        r = _np(batch.rho[i])
+        assert np.abs(m - mom1).max() < 1e-12, (wl.name, np.abs(m - mom1).max())
+        assert abs(mu[i] - mu1) < 1e-11, (wl.name, mu[i], mu1)
+        assert np.abs(r - rho1).max() < tol_rho * rho1.max(), wl.name
+        assert np.abs(e[i] - e1).max() < 1e-10 * np.abs(e1).max(), wl.name
+        assert abs(e[i][3] - wl.n_electrons) < 1e-10 * wl.n_electrons
+
+
+def test_batch_matches_single_snapshots_and_oracle():
+    sq = _sq()
+    wls = _small_ensemble()
+    print("case small ensemble fp64 eager", flush=True)
+    snaps = _snaps(wls)
+    ref = _single(snaps, wls)
+    b = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=False)
+    mu, e = b.step()
+    _compare(b, mu, e, ref, wls)
+    # the tiny snapshot against the oracle (bounds of the GPU, density at the GPU's mu)
+    wl = wls[0]
+    o = oracle.Oracle.from_workload(wl, veff=wl.veff())
+    lmin, lmax = o.bounds()
+    mom_ref = o.moments(lmin, lmax)
+    assert np.abs(_np(b.moments[0]) - mom_ref).max() < 1e-8  # bounds differ at rounding level
+    mu_ref, _ = o.fermi_level(lmin, lmax, mom_ref, wl.n_electrons)
+    assert abs(mu[0] - mu_ref) < 1e-8
+    rho_ref, e_ref = o.density_energy(lmin, lmax, mom_ref, mu[0])
+    r = _np(b.rho[0])
+    assert np.abs(r - rho_ref).max() < 1e-8 * rho_ref.max()
+
+
+def test_batch_graph_replays_match_eager():
+    sq = _sq()
+    wls = _small_ensemble()
+    print("case small ensemble fp64 graph", flush=True)
+    snaps = _snaps(wls)
+    ref = _single(snaps, wls)
+    b = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=True)
+    for rep in range(3):
+        mu, e = b.step()
+        _compare(b, mu, e, ref, wls)
+        # eager work of the program between replays
+        snaps[0].spectral_bounds()
+        snaps[0].moments()
+        torch.cuda.synchronize()
+
+
+def test_batch_mixed_precision():
+    sq = _sq()
+    wls = _small_ensemble("mixed")[:3]
+    print("case small ensemble mixed", flush=True)
+    snaps = _snaps(wls)
+    ref = _single(snaps, wls)
+    b = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=True)
+    mu, e = b.step()
+    for i, wl in enumerate(wls):
+        rho1 = ref[i][2]
+        r = _np(b.rho[i])
+        # same kernels; FP32 rounding can flip where projector-dot atomics
+        # change the FP64 summation order
+        assert np.abs(r - rho1).max() < 1e-7 * rho1.max(), wl.name
+        assert abs(e[i][3] - wl.n_electrons) < 1e-9 * wl.n_electrons
+
+
+def test_batch_autotune_and_cache(tmp_path):
+    sq = _sq()
+    wls = _small_ensemble()[:3]
+    print("case autotune", flush=True)
+    snaps = _snaps(wls)
+    ref = _single(snaps, wls)
+    cache = str(tmp_path / "tiles.json")
+    b = sq.Batch(snaps, [wl.n_electrons for wl in wls])
+    t = b.autotune(cache)
+    assert t["block_nodes"] in (8, 32, 128) and t["n_items"] > 0
+    data = json.load(open(cache))
+    assert len(data) == 1
+    entry = next(iter(data.values()))
+    assert entry["block_nodes"] == t["block_nodes"] and entry["wg_per_cu"] == t["wg_per_cu"]
+    mu, e = b.step()
+    _compare(b, mu, e, ref, wls)
+    # a second batch of the same shapes reads the cache
+    b2 = sq.Batch(snaps, [wl.n_electrons for wl in wls])
+    t2 = b2.autotune(cache)
+    assert t2["block_nodes"] == t["block_nodes"] and t2["wg_per_cu"] == t["wg_per_cu"]
+    assert len(json.load(open(cache))) == 1
+
+
+def test_batch_ensemble_sampled():
+    """The 12-snapshot ensemble (32-500 atoms, cubes 21-37, n_pl 32-64, FP32-mixed)
+    in one batched pass; sampled nodes of every snapshot against the oracle."""
+    sq = _sq()
+    wls = W.qmd_ensemble()
+    print(f"case qmd ensemble: {len(wls)} snapshots", flush=True)
+    snaps = _snaps(wls)
+    b = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=True)
+    mu, e = b.step()
+    rng = np.random.default_rng(7)
+    for i, (wl, g) in enumerate(zip(wls, snaps)):
+        print(f"  {wl.name}: n={wl.n} mu={mu[i]:.10f} N={e[i][3]:.10f}", flush=True)
+        assert abs(e[i][3] - wl.n_electrons) < 1e-9 * wl.n_electrons
+        # FP64 reference on two sampled nodes, on FP64 bounds from the oracle
+        nodes = rng.choice(g.nd, 2, replace=False)
+        o = oracle.Oracle.from_workload(wl, veff=wl.veff())
+        lo, hi = o.bounds(nodes)
+        mom_ref = o.moments(lo, hi, nodes=nodes)
+        rho_ref, _ = o.density_energy(lo, hi, mom_ref, mu[i])
+        r = _np(b.rho[i])
+        err = np.abs(r[nodes] - rho_ref).max() / r.max()
+        print(f"    sampled rho rel err {err:.2e}", flush=True)
+        assert err < 2e-5

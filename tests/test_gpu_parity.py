@@ -198,6 +198,51 @@ def test_large_cell_sampled():
     _sampled_parity(wl, 12, seed=1)
 
 
+# Regions wider than 31 points stream the current vector through the
+# workgroup's buffers (three columns per thread); the cube is larger than the
+# 16^3 cell here, so it wraps the periodic cell twice.
+STREAMED = {
+    # name: (rcut, npl, seed)
+    "streamed_cube33": (8.0, 16, 11),
+    "streamed_cube35": (8.5, 12, 12),
+    "streamed_cube37": (9.0, 16, 13),
+}
+
+
+@pytest.mark.parametrize("name", sorted(STREAMED))
+def test_streamed_cubes_sampled(name):
+    rc, npl, seed = STREAMED[name]
+    wl = W.fcc_workload(name, 1, 8.0, 0.1, seed, 0.5, rc, npl, 1.0)
+    print(f"case {name} n={wl.n} C={2 * int(rc / wl.h_eff + 0.5) + 1}", flush=True)
+    _sampled_parity(wl, 6, seed=seed)
+
+
+def test_streamed_cube_mixed():
+    sq = _sq()
+    wl = W.fcc_workload("streamed_cube33_mixed", 1, 8.0, 0.1, 11, 0.5, 8.0, 24, 1.0)
+    print(f"case {wl.name}", flush=True)
+    V, ref, g = _pair(wl)
+    gm = sq.SQ.from_workload(wl, veff=torch.from_numpy(V).cuda(), precision=sq.FP32_MIXED)
+    glo, ghi = g.spectral_bounds()
+    mom = g.moments()
+    mu = g.fermi_level(mom, wl.n_electrons)
+    rho64, _ = g.density_energy(mom, mu)
+    gm.set_bounds(glo, ghi)
+    rhom, em = gm.density_energy(gm.moments(), mu)
+    glo, ghi, r64, rm = _np(glo), _np(ghi), _np(rho64), _np(rhom)
+    nodes = np.unique(np.concatenate([[0, g.nd // 3, g.nd - 1],
+                                      np.random.default_rng(5).choice(g.nd, 5, replace=False)]))
+    mom_ref = ref.moments(glo[nodes], ghi[nodes], nodes=nodes)
+    rho_ref, _ = ref.density_energy(glo[nodes], ghi[nodes], mom_ref, mu)
+    assert np.abs(r64[nodes] - rho_ref).max() < 1e-10 * r64.max()
+    err = np.abs(rm[nodes] - rho_ref).max() / r64.max()
+    print(f"mixed rho rel err (sampled) {err:.3e}", flush=True)
+    assert err < 1e-5
+    full = np.abs(rm - r64).max() / r64.max()
+    print(f"mixed rho rel err vs FP64 (all nodes) {full:.3e}", flush=True)
+    assert full < 1e-5
+
+
 def test_error_paths():
     sq = _sq()
     wl = W.tiny_cell()
