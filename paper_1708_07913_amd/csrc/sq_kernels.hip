@@ -40,7 +40,11 @@ struct Shape {
     static constexpr int RB = rows_per_thread(C);
     static constexpr int CC = C * C;
     static constexpr int YP = (C + RB - 1) / RB;            // row groups
-    static constexpr int NT = C * YP;                        // threads owning columns
+    // 29- and 31-point cubes give each row group 32 lanes (the last idle or
+    // two): a half-wave then reads 32 consecutive plane entries, which keeps
+    // the 64-bit LDS reads free of bank conflicts
+    static constexpr int XW = (C == 29 || C == 31) ? 32 : C;  // threads per row group
+    static constexpr int NT = XW * YP;                       // threads owning row groups
     static constexpr int P = C + 2 * NO;                     // padded plane edge (zero halo NO)
     static constexpr int ROWS = P + 2 * NO + RB;             // + an all-zero neighbourhood for idle threads
     static constexpr int PLANE = ROWS * P + 1;               // + one write-only cell for idle threads
@@ -136,6 +140,15 @@ __device__ __forceinline__ double uniform(double v) {
     const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
     const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
     return __hiloint2double(hi, lo);
+}
+
+// The thread index as a value the compiler cannot relate to earlier uses:
+// addresses derived from it are formed where they are needed instead of being
+// kept live (and spilled) through the unrolled sweeps.
+__device__ __forceinline__ int fresh_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
 }
 
 // Butterfly sum over the 64 lanes.  The lane index is made opaque so that the
@@ -426,17 +439,25 @@ struct Cols {
     int pcw[RB];                // LDS write offset of the column's plane value
     __device__ __forceinline__ void init(int tid) {
         const bool t_active = tid < S::NT;
-        x = t_active ? tid % C : 0;
-        y0 = t_active ? (tid / C) * RB : 0;
+        x = t_active ? tid % S::XW : 0;
+        y0 = t_active ? (tid / S::XW) * RB : 0;
+        // lanes past the cube's x range read (and discard) the next padded row
         corner = t_active ? y0 * S::P + x : S::IDLE_CORNER;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const bool ok = t_active && (y0 + r < C);
+            const bool ok = t_active && (x < C) && (y0 + r < C);
             col[r] = ok ? (y0 + r) * C + x : -1;
             pcw[r] = ok ? corner + (NO + r) * S::P + NO : S::IDLE_WRITE;
         }
     }
     __device__ __forceinline__ bool valid(int r) const { return col[r] >= 0; }
+    // col[r] recomputed from a fresh thread index (see fresh_tid)
+    __device__ __forceinline__ static int column(int r) {
+        const int t = fresh_tid();
+        if (t >= S::NT) return -1;
+        const int xx = t % S::XW, yy = (t / S::XW) * RB + r;
+        return (xx < C && yy < C) ? yy * C + xx : -1;
+    }
 };
 
 // Position the chains of a column at their first records and fetch plane 0.
@@ -484,7 +505,7 @@ __device__ __forceinline__ void projector_dots(Lds<C, T, NCH> &L, __amdgpu_buffe
     constexpr int RB = Shape<C>::RB;
     Chain ch[RB][NCH];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) chains_start(L, pvr, cl.col[r], ch[r], nch);
+    for (int r = 0; r < RB; ++r) chains_start(L, pvr, Cols<C>::column(r), ch[r], nch);
 #pragma unroll
     for (int z = 0; z < C; ++z) {
 #pragma unroll
@@ -691,11 +712,11 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
         for (int k = 0; k < half; ++k) {
             const double al = k == 0 ? 1.0 : 2.0;
             const double scale = uniform(al * invz);
-            for (int i = tid; i < kMaxImages; i += S::BLOCK)
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK)
                 L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur][i] : 0.0;
             Chain ch[RB][NCH];
 #pragma unroll
-            for (int r = 0; r < RB; ++r) chains_start(L, pvr, cl.col[r], ch[r], nch);
+            for (int r = 0; r < RB; ++r) chains_start(L, pvr, Cols<C>::column(r), ch[r], nch);
             double *snext = L.s[cur ^ 1];
             double d1 = 0.0, d2 = 0.0;
             unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
@@ -821,7 +842,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
                         }
                     }
             }
-            for (int i = tid; i < kMaxImages; i += S::BLOCK) L.s[cur][i] = 0.0;
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) L.s[cur][i] = 0.0;
             cur ^= 1;
             __syncthreads();
         }
@@ -956,7 +977,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
             // -> wslot.  The projector part, sum_I c_I (p_I . v_j) p_I, is added
             // in the second pass, where the same walk over the projector runs
             // also forms p . w; its contribution to alpha is sum_I c_I (p_I . v_j)^2.
-            for (int i = tid; i < kMaxImages; i += S::BLOCK)
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK)
                 L.cs[i] = i < ni ? L.img_coef[i] * L.s[cur][i] : 0.0;
             unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
             asm volatile("" : "+s"(zb));
@@ -1010,7 +1031,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
             }
             __syncthreads();
             double dimg = 0.0;
-            for (int i = tid; i < ni; i += S::BLOCK) dimg += L.cs[i] * L.s[cur][i];
+            for (int i = fresh_tid(); i < ni; i += S::BLOCK) dimg += L.cs[i] * L.s[cur][i];
             block_sum2(L, da, dimg, tid);
             const double alpha = uniform(scx * da + dimg);
             double dummy = 0.0;
@@ -1023,7 +1044,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
             double db = 0.0;
             Chain ch[RB][NCH];
 #pragma unroll
-            for (int r = 0; r < RB; ++r) chains_start(L, pvr, cl.col[r], ch[r], nch);
+            for (int r = 0; r < RB; ++r) chains_start(L, pvr, Cols<C>::column(r), ch[r], nch);
             double un[2][RB], xn[2][RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
@@ -1087,7 +1108,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
             }
             scy = scx;
             scx = rb;
-            for (int i = tid; i < kMaxImages; i += S::BLOCK) {
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) {
                 L.s[cur ^ 1][i] = L.s[cur ^ 1][i] * rb;
                 L.s[cur][i] = 0.0;
             }
