@@ -46,9 +46,10 @@ struct Shape {
     static constexpr int XW = (C == 29 || C == 31) ? 32 : C;  // threads per row group
     static constexpr int NT = XW * YP;                       // threads owning row groups
     static constexpr int P = C + 2 * NO;                     // padded plane edge (zero halo NO)
-    static constexpr int ROWS = P + 2 * NO + RB;             // + an all-zero neighbourhood for idle threads
+    // + RB + 1 rows read (and discarded) by columns past the cube edge
+    static constexpr int ROWS = P + RB + 1;
     static constexpr int PLANE = ROWS * P + 1;               // + one write-only cell for idle threads
-    static constexpr int IDLE_CORNER = P * P;
+    static constexpr int IDLE_CORNER = 0;                    // idle threads read real cells and discard them
     static constexpr int IDLE_WRITE = ROWS * P;
     static constexpr int BLOCK = (NT + 63) / 64 * 64;
     static constexpr int NW = BLOCK / 64;
@@ -57,6 +58,8 @@ struct Shape {
     // wider regions stream it through the workgroup's buffers with a window of
     // 2 NO + 2 planes in registers
     static constexpr bool STREAM = C > kResidentCube;
+    // plane buffers: resident cubes sweep Lanczos two planes per barrier
+    static constexpr int NBUF = STREAM ? 2 : 4;
     static constexpr int CPT = (CC + BLOCK - 1) / BLOCK;     // columns per thread in the set-up scan
 };
 
@@ -68,7 +71,7 @@ constexpr unsigned kIdleOffset = 0x7FFFFF00u;  // beyond every buffer: loads rea
 
 template <int C, typename T, int NCH>
 struct Lds {
-    T plane[2][Shape<C>::PLANE];
+    T plane[Shape<C>::NBUF][Shape<C>::PLANE];  // double-buffered groups of planes
     uint2 runs[Shape<C>::MAXRUNS + 1];
     int col_start[Shape<C>::CC + 1];
     int col_fill[Shape<C>::CC];
@@ -232,7 +235,7 @@ __device__ void setup_region(const AT &A, Lds<C, T, NCH> &L, int qi, int qj, int
         L.nch = 1;
         L.runs[S::MAXRUNS] = make_uint2(kSentinelX, 0u);
     }
-    for (int i = tid; i < 2 * S::PLANE; i += S::BLOCK) (&L.plane[0][0])[i] = T(0);
+    for (int i = tid; i < S::NBUF * S::PLANE; i += S::BLOCK) (&L.plane[0][0])[i] = T(0);
     for (int i = tid; i < S::CC; i += S::BLOCK) L.col_fill[i] = 0;
     for (int i = tid; i < kMaxImages; i += S::BLOCK) L.s[0][i] = L.s[1][i] = 0.0;
     __syncthreads();
@@ -989,44 +992,71 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
 #pragma unroll
                     for (int r = 0; r < RB; ++r) tv[r][z] = bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u);
             }
+            // PPB planes per barrier (resident cubes: two, with four plane
+            // buffers); the loads of the next group are issued while this
+            // group is processed
+            constexpr int PPB = S::NBUF / 2;
             double da = 0.0;
-            double vzn[RB], vpn[RB];
+            double vzn[PPB][RB], vpn[PPB][RB];
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * (zb % (unsigned)n) * 8u);
-                vpn[r] = 0.0;
-                if (j > 0) vpn[r] = sprev * bload<double>(prev, voff[r], 0u);
-            }
-#pragma unroll
-            for (int z = 0; z < C; ++z) {
-                const unsigned sz = (unsigned)(z * S::CC) * 8u;
-                double vz[RB], vprev[RB];
+            for (int h = 0; h < PPB; ++h)
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    vz[r] = vzn[r];
-                    vprev[r] = vpn[r];
-                    if (z + 1 < C) {
-                        const unsigned sz1 = (unsigned)((z + 1) * S::CC) * 8u;
-                        vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)(z + 1)) % (unsigned)n) * 8u);
-                        if (j > 0) vpn[r] = sprev * bload<double>(prev, voff[r], sz1);
+                    vzn[h][r] = 0.0;
+                    vpn[h][r] = 0.0;
+                    if (h < C) {
+                        vzn[h][r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)h) % (unsigned)n) * 8u);
+                        if (j > 0) vpn[h][r] = sprev * bload<double>(prev, voff[r], (unsigned)(h * S::CC) * 8u);
                     }
-                    if (kStream && z + ZA < C)
-                        tv[r][z + ZA] = bload<double>(slr, voff[r], (unsigned)((z + ZA) * S::CC) * 8u);
-                    L.plane[z & 1][cl.pcw[r]] = tv[r][z];
+                }
+#pragma unroll
+            for (int z0 = 0; z0 < C; z0 += PPB) {
+                const int pb = PPB * ((z0 / PPB) & 1);
+                double vz[PPB][RB], vprev[PPB][RB];
+#pragma unroll
+                for (int h = 0; h < PPB; ++h)
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) {
+                        vz[h][r] = vzn[h][r];
+                        vprev[h][r] = vpn[h][r];
+                        const int zn = z0 + h + PPB;
+                        if (zn < C) {
+                            vzn[h][r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)zn) % (unsigned)n) * 8u);
+                            if (j > 0) vpn[h][r] = sprev * bload<double>(prev, voff[r], (unsigned)(zn * S::CC) * 8u);
+                        }
+                    }
+#pragma unroll
+                for (int h = 0; h < PPB; ++h) {
+                    const int z = z0 + h;
+                    if (z < C) {
+#pragma unroll
+                        for (int r = 0; r < RB; ++r) {
+                            if (kStream && z + ZA < C)
+                                tv[r][z + ZA] = bload<double>(slr, voff[r], (unsigned)((z + ZA) * S::CC) * 8u);
+                            L.plane[pb + h][cl.pcw[r]] = tv[r][z];
+                        }
+                    }
                 }
                 __syncthreads();
-                const PlaneView<C, double> pv(L.plane[0], z & 1, cl.corner);
-                double yrow[2 * NO + RB];
-                load_yrows<C, double>(pv, tv, z, yrow);
 #pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                    double u = scx * (stencil_sum<C, double>(pv, yrow, tv[r], r, z, kw) + (vz[r] + kin0) * tv[r][z]);
-                    u -= bprev * vprev[r];
-                    if (!cl.valid(r)) u = 0.0;  // column past the cube edge stays zero
-                    if (!kStream) bstore(tv[r][z], slr, voff[r], sz);
-                    bstore(u, wlr, voff[r], sz);
-                    da += u * tv[r][z];
-                    pin(da);
+                for (int h = 0; h < PPB; ++h) {
+                    const int z = z0 + h;
+                    if (z < C) {
+                        const unsigned sz = (unsigned)(z * S::CC) * 8u;
+                        const PlaneView<C, double> pv(L.plane[0], pb + h, cl.corner);
+                        double yrow[2 * NO + RB];
+                        load_yrows<C, double>(pv, tv, z, yrow);
+#pragma unroll
+                        for (int r = 0; r < RB; ++r) {
+                            double u = scx * (stencil_sum<C, double>(pv, yrow, tv[r], r, z, kw) + (vz[h][r] + kin0) * tv[r][z]);
+                            u -= bprev * vprev[h][r];
+                            if (!cl.valid(r)) u = 0.0;  // column past the cube edge stays zero
+                            if (!kStream) bstore(tv[r][z], slr, voff[r], sz);
+                            bstore(u, wlr, voff[r], sz);
+                            da += u * tv[r][z];
+                            pin(da);
+                        }
+                    }
                 }
             }
             __syncthreads();
