@@ -127,6 +127,38 @@ def run_ensemble(args):
     print(json.dumps(rec), flush=True)
 
 
+def run_mixed_sweep():
+    """FP32-mixed against the FP64 path on the tiny cell for kT in {0.5, 1, 2, 5} eV
+    and n_pl in {32, 48, 96}: the FP64 bounds and Fermi level are injected, so the
+    errors are those of the mixed recurrence alone (the FP64 path itself matches
+    the oracle to 1e-10 in the parity tests)."""
+    import torch
+    from paper_1708_07913_amd import sq
+    from paper_1708_07913_amd import workloads as W
+
+    rows = []
+    for kT in (0.5, 1.0, 2.0, 5.0):
+        for npl in (32, 48, 96):
+            wl = W.tiny_cell("mixed", npl=npl, kT_eV=kT)
+            V = torch.from_numpy(wl.veff()).cuda()
+            g = sq.SQ.from_workload(wl, veff=V, precision=sq.FP64)
+            mom, mu, rho64, e64 = g.scf_pass(wl.n_electrons)
+            lmin, lmax = g.spectral_bounds()
+            gm = sq.SQ.from_workload(wl, veff=V, precision=sq.FP32_MIXED)
+            gm.set_bounds(lmin, lmax)
+            rho, e = gm.density_energy(gm.moments(), mu)
+            torch.cuda.synchronize()
+            r, r64 = rho.cpu().numpy(), rho64.cpu().numpy()
+            rows.append({"kT_eV": kT, "npl": npl,
+                         "rho_max_rel_err": float(np.abs(r - r64).max() / r64.max()),
+                         "E_band_err_Ha_per_atom": float(abs(e[0] - e64[0]) / wl.natom),
+                         "F_err_Ha_per_atom": float(abs(e[2] - e64[2]) / wl.natom),
+                         "electron_count_err": float(abs(e[3] - e64[3]))})
+            print(f"[bench] mixed sweep kT={kT} npl={npl}: {rows[-1]}", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "al4_h0.5_rc2.5 mixed-precision sweep", "reference": "FP64 GPU path",
+                      "rows": rows, "max_rho_rel_err": max(x["rho_max_rel_err"] for x in rows)}), flush=True)
+
+
 def cpu_baseline(wl, budget_s=20.0):
     """The FP64 oracle on a bounded node sample of the same workload (bounds +
     moments, the per-node work of a step), scaled to node-steps per second."""
@@ -155,7 +187,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="paper", choices=["paper", "paper-small", "large", "tiny", "ensemble"])
+    ap.add_argument("--workload", default="paper",
+                    choices=["paper", "paper-small", "large", "tiny", "ensemble", "mixed-sweep"])
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"],
                     help="precision of the ensemble workload")
     ap.add_argument("--no-mixed", action="store_true")
@@ -185,6 +218,9 @@ def main():
         print("[bench] copy calibration: 1 GiB device-to-device", file=sys.stderr, flush=True)
     if args.workload == "ensemble":
         run_ensemble(args)
+        return
+    if args.workload == "mixed-sweep":
+        run_mixed_sweep()
         return
     wl = workload(args.workload)
     print(f"[bench] {wl.name}: n={wl.n} natom={wl.natom} npl={wl.npl}", file=sys.stderr, flush=True)

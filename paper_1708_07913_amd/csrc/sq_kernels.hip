@@ -431,6 +431,49 @@ struct Chain {
     }
 };
 
+// The same walk for register-only passes (no barrier to hide latency
+// behind): values are fetched two planes ahead, from the current record or
+// the next one (after plane z the current record ends at z + 1 or later, so
+// plane z + 2 lies in the current record, in the next one, or in neither).
+struct Chain2 {
+    int i, e;
+    unsigned rx, nrx;  // current and next record: slot | z_first << 8 | z_last << 16
+    int vb, nvb;       // their value bases
+    double acc;
+    double pv[2];      // values of planes z and z + 1 (indexed by plane parity)
+
+    __device__ __forceinline__ int sl() const { return (int)(rx & 0xFFu); }
+    __device__ __forceinline__ int z1() const { return (int)((rx >> 16) & 0xFFu); }
+    __device__ __forceinline__ void start(const uint2 *runs, int b, int end, int sentinel) {
+        i = b;
+        e = end;
+        acc = 0.0;
+        const uint2 r0 = runs[i < e ? i : sentinel], r1 = runs[i + 1 < e ? i + 1 : sentinel];
+        rx = r0.x;
+        vb = (int)r0.y;
+        nrx = r1.x;
+        nvb = (int)r1.y;
+    }
+    __device__ __forceinline__ void fetch(__amdgpu_buffer_rsrc_t pvr, int z) {
+        const bool cur = (z >= (int)((rx >> 8) & 0xFFu)) & (z <= (int)((rx >> 16) & 0xFFu));
+        const bool nxt = (z >= (int)((nrx >> 8) & 0xFFu)) & (z <= (int)((nrx >> 16) & 0xFFu));
+        const unsigned off = cur ? (unsigned)(vb + z) * 8u : (nxt ? (unsigned)(nvb + z) * 8u : kIdleOffset);
+        pv[z & 1] = bload<double>(pvr, off, 0u);
+    }
+    __device__ __forceinline__ void finish(double *s, int z, const uint2 *runs, int sentinel) {
+        if (z == z1()) {
+            atomicAdd(&s[sl()], acc);
+            acc = 0.0;
+            ++i;
+            rx = nrx;
+            vb = nvb;
+            const uint2 r1 = runs[i + 1 < e ? i + 1 : sentinel];
+            nrx = r1.x;
+            nvb = (int)r1.y;
+        }
+    }
+};
+
 // Columns owned by one thread and their per-column addressing.
 template <int C>
 struct Cols {
@@ -481,6 +524,38 @@ __device__ __forceinline__ void chains_start(const Lds<C, T, NCH> &L, __amdgpu_b
     }
 }
 
+template <int C, typename T, int NCH>
+__device__ __forceinline__ void chains2_start(const Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr, int column,
+                                              Chain2 (&ch)[NCH], int nch) {
+    constexpr int SENT = Shape<C>::MAXRUNS;
+    const bool ok = column >= 0;
+    const int b = ok ? L.col_start[column] : 0;
+    const int e = ok ? L.col_start[column + 1] : 0;
+#pragma unroll
+    for (int ci = 0; ci < NCH; ++ci) {
+        const int s0 = b + (ok ? L.col_off[column][ci] : 0);
+        const int s1 = ci + 1 < NCH ? b + (ok ? L.col_off[column][ci + 1] : 0) : e;
+        ch[ci].start(L.runs, s0, s1, SENT);
+        ch[ci].pv[0] = ch[ci].pv[1] = 0.0;
+        if (ci == 0 || ci < nch) {
+            ch[ci].fetch(pvr, 0);
+            if (C > 1) ch[ci].fetch(pvr, 1);
+        }
+    }
+}
+
+template <int C, int NCH>
+__device__ __forceinline__ void chains2_advance(Chain2 (&ch)[NCH], double *s_dst, const uint2 *runs,
+                                                __amdgpu_buffer_rsrc_t pvr, int z, int nch) {
+#pragma unroll
+    for (int ci = 0; ci < NCH; ++ci) {
+        if (ci == 0 || ci < nch) {
+            ch[ci].finish(s_dst, z, runs, Shape<C>::MAXRUNS);
+            if (z + 2 < C) ch[ci].fetch(pvr, z + 2);
+        }
+    }
+}
+
 // After plane z of a column: close finished runs into s_dst and fetch plane z + 1.
 template <int C, int NCH>
 __device__ __forceinline__ void chains_advance(Chain (&ch)[NCH], double *s_dst, const uint2 *runs,
@@ -502,26 +577,49 @@ __device__ __forceinline__ void node_coords(long long q, int n, int &qi, int &qj
 
 // Projector dots of a vector given plane by plane: s[dst][I] += p_I . t, with
 // t(r, z) the value of the thread's column r at plane z.
-template <int C, typename T, int NCH, typename F>
+// AHEAD2 selects the two-plane look-ahead walk (Chain2); the moments kernel
+// keeps the one-plane walk, which leaves its register allocation unchanged.
+template <bool AHEAD2, int C, typename T, int NCH, typename F>
 __device__ __forceinline__ void projector_dots(Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr, const Cols<C> &cl,
                                                int dst, int nch, F &&t) {
     constexpr int RB = Shape<C>::RB;
-    Chain ch[RB][NCH];
+    if constexpr (AHEAD2) {
+        Chain2 ch[RB][NCH];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) chains_start(L, pvr, Cols<C>::column(r), ch[r], nch);
+        for (int r = 0; r < RB; ++r) chains2_start(L, pvr, Cols<C>::column(r), ch[r], nch);
 #pragma unroll
-    for (int z = 0; z < C; ++z) {
+        for (int z = 0; z < C; ++z) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const double v = t(r, z);
+            for (int r = 0; r < RB; ++r) {
+                const double v = t(r, z);
 #pragma unroll
-            for (int ci = 0; ci < NCH; ++ci) {
-                if (ci == 0 || ci < nch) {
-                    ch[r][ci].acc += ch[r][ci].pv * v;
-                    pin(ch[r][ci].acc);
+                for (int ci = 0; ci < NCH; ++ci) {
+                    if (ci == 0 || ci < nch) {
+                        ch[r][ci].acc += ch[r][ci].pv[z & 1] * v;
+                        pin(ch[r][ci].acc);
+                    }
                 }
+                chains2_advance<C, NCH>(ch[r], L.s[dst], L.runs, pvr, z, nch);
             }
-            chains_advance<C, NCH>(ch[r], L.s[dst], L.runs, pvr, z, nch);
+        }
+    } else {
+        Chain ch[RB][NCH];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) chains_start(L, pvr, Cols<C>::column(r), ch[r], nch);
+#pragma unroll
+        for (int z = 0; z < C; ++z) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const double v = t(r, z);
+#pragma unroll
+                for (int ci = 0; ci < NCH; ++ci) {
+                    if (ci == 0 || ci < nch) {
+                        ch[r][ci].acc += ch[r][ci].pv * v;
+                        pin(ch[r][ci].acc);
+                    }
+                }
+                chains_advance<C, NCH>(ch[r], L.s[dst], L.runs, pvr, z, nch);
+            }
         }
     }
     __syncthreads();
@@ -706,7 +804,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
         if (tid == 0) mrow[0] = 1.0;
         int cur = 0;
         // streamed mode: t^0 goes to X here, so that every sweep reads X
-        projector_dots(L, pvr, cl, cur, nch, [&](int r, int z) {
+        projector_dots<false>(L, pvr, cl, cur, nch, [&](int r, int z) {
             const T v = e_q(r, z);
             if (kStream) bstore(v, slr, voff[r], (unsigned)(z * S::CC) * (unsigned)sizeof(T));
             return (double)v;
@@ -963,7 +1061,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
         }
         int cur = 0;
         // streamed mode: v_1 goes to X here, so that every sweep reads X
-        projector_dots(L, pvr, cl, cur, nch, [&](int r, int z) {
+        projector_dots<true>(L, pvr, cl, cur, nch, [&](int r, int z) {
             if (!kStream) return tv[r][z];
             const double v = start(r, z);
             bstore(v, slr, voff[r], (unsigned)(z * S::CC) * 8u);
@@ -1072,9 +1170,9 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
             // |alpha/beta| per step).  Loads of planes z + 1 and z + 2 are in
             // flight while plane z is processed.
             double db = 0.0;
-            Chain ch[RB][NCH];
+            Chain2 ch[RB][NCH];
 #pragma unroll
-            for (int r = 0; r < RB; ++r) chains_start(L, pvr, Cols<C>::column(r), ch[r], nch);
+            for (int r = 0; r < RB; ++r) chains2_start(L, pvr, Cols<C>::column(r), ch[r], nch);
             double un[2][RB], xn[2][RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
@@ -1098,7 +1196,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
                     }
 #pragma unroll
                     for (int ci = 0; ci < NCH; ++ci)
-                        if (ci == 0 || ci < nch) uz += L.cs[ch[r][ci].sl()] * ch[r][ci].pv;
+                        if (ci == 0 || ci < nch) uz += L.cs[ch[r][ci].sl()] * ch[r][ci].pv[z & 1];
                     double w = uz - alpha * vj;
                     if (!cl.valid(r)) w = 0.0;
                     if (kStream) bstore(w, sly, voff[r], (unsigned)(z * S::CC) * 8u);
@@ -1108,11 +1206,11 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
 #pragma unroll
                     for (int ci = 0; ci < NCH; ++ci) {
                         if (ci == 0 || ci < nch) {
-                            ch[r][ci].acc += ch[r][ci].pv * w;
+                            ch[r][ci].acc += ch[r][ci].pv[z & 1] * w;
                             pin(ch[r][ci].acc);
                         }
                     }
-                    chains_advance<C, NCH>(ch[r], L.s[cur ^ 1], L.runs, pvr, z, nch);
+                    chains2_advance<C, NCH>(ch[r], L.s[cur ^ 1], L.runs, pvr, z, nch);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
