@@ -178,6 +178,14 @@ typedef struct sq_batch_options {
     int wg_per_cu;       /* persistent workgroups per compute unit (0: occupancy limit) */
     int use_graph;       /* 1 (default): capture the pass as a hipGraph on the first
                             sq_batch_step and replay it afterwards; 0: plain launches */
+    int bounds_every;    /* recompute the Lanczos bounds at least every this many
+                            passes (default 1: every pass).  In between, the previous
+                            chi and zeta are reused while V_eff has moved by at most
+                            half of the margin slack min_q zeta_q margin/(1+margin)
+                            since they were computed (V_eff enters H_q as a diagonal:
+                            no eigenvalue moves further than max|delta V|); otherwise,
+                            or if a moment leaves [-1, 1], the pass computes fresh
+                            bounds. */
 } sq_batch_options;
 
 void sq_batch_default_options(sq_batch_options *opt);

@@ -370,14 +370,20 @@ struct sq_batch {
     char *ws = nullptr;
     hipStream_t own = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};       // [0]: bounds reused, [1]: with bounds
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    long long passes = 0;
+    bool have_bounds = false;
+    std::vector<double> slack;       // per snapshot: min_q zeta_q margin / (1 + margin) of the last bounds
+    size_t off_vref = 0, off_red = 0;  // V_eff at the last bounds; reduction outputs (2 per snapshot)
 
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
     ~sq_batch() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        for (int i = 0; i < 2; ++i) {
+            if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+            if (graph[i]) (void)hipGraphDestroy(graph[i]);
+        }
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (own) (void)hipStreamDestroy(own);
@@ -387,10 +393,12 @@ struct sq_batch {
 namespace {
 
 void drop_graph(sq_batch *b) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
+    for (int i = 0; i < 2; ++i) {
+        if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+        if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+        b->exec[i] = nullptr;
+        b->graph[i] = nullptr;
+    }
 }
 
 int batch_grid(const sq_batch *b, const sq_batch::Group &g, bool lanczos) {
@@ -485,8 +493,8 @@ int enqueue_recurrences(sq_batch *b, bool lanczos, bool moments, hipStream_t s) 
 }
 
 // The whole pass, without host round trips (so that it can be captured).
-int enqueue_pass(sq_batch *b, hipStream_t s) {
-    int rc = enqueue_recurrences(b, true, true, s);
+int enqueue_pass(sq_batch *b, bool bounds, hipStream_t s) {
+    int rc = enqueue_recurrences(b, bounds, true, s);
     if (rc) return rc;
     const int n = int(b->ctx.size());
     for (int i = 0; i < n; ++i) {
@@ -578,6 +586,64 @@ int finish_pass(sq_batch *b, hipStream_t s, double *mu, double *energies) {
     return SQ_OK;
 }
 
+// Reusing bounds is safe while V_eff has moved by less than half the margin
+// slack since they were computed: the potential enters H_q as a diagonal, so
+// by Weyl's inequality no eigenvalue moves further than max |delta V|.
+int reuse_is_safe(sq_batch *b, hipStream_t s, bool *safe) {
+    const size_t n = b->ctx.size();
+    double *out = b->at<double>(b->off_red);
+    size_t vo = 0;
+    for (size_t i = 0; i < n; ++i) {
+        sq_ctx *c = b->ctx[i];
+        int rc = hip_check(sq::launch_diff_extent(c->veff, b->at<double>(b->off_vref) + vo, c->nd,
+                                                  b->at<double>(b->off_part), kReduceBlocks, out + 2 * i, s),
+                           "potential change");
+        if (rc) return rc;
+        vo += size_t(c->nd);
+    }
+    std::vector<double> ext(2 * n);
+    int rc = hip_check(hipMemcpyAsync(ext.data(), out, 2 * n * sizeof(double), hipMemcpyDeviceToHost, s),
+                       "potential change");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "potential change");
+    if (rc) return rc;
+    *safe = true;
+    for (size_t i = 0; i < n; ++i) {
+        const double dv = std::max(-ext[2 * i], ext[2 * i + 1]);
+        if (!(dv <= 0.5 * b->slack[i])) *safe = false;
+    }
+    return SQ_OK;
+}
+
+// After a pass that computed bounds: remember V_eff and the margin slack.
+int record_bounds(sq_batch *b, hipStream_t s) {
+    const size_t n = b->ctx.size();
+    double *out = b->at<double>(b->off_red);
+    size_t vo = 0;
+    for (size_t i = 0; i < n; ++i) {
+        sq_ctx *c = b->ctx[i];
+        int rc = hip_check(hipMemcpyAsync(b->at<double>(b->off_vref) + vo, c->veff, size_t(c->nd) * sizeof(double),
+                                          hipMemcpyDeviceToDevice, s),
+                           "keeping V_eff");
+        if (!rc)
+            rc = hip_check(sq::launch_diff_extent(c->at<double>(c->off_zeta), nullptr, c->nd,
+                                                  b->at<double>(b->off_part), kReduceBlocks, out + 2 * i, s),
+                           "margin slack");
+        if (rc) return rc;
+        vo += size_t(c->nd);
+    }
+    std::vector<double> ext(2 * n);
+    int rc = hip_check(hipMemcpyAsync(ext.data(), out, 2 * n * sizeof(double), hipMemcpyDeviceToHost, s),
+                       "margin slack");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "margin slack");
+    if (rc) return rc;
+    b->slack.assign(n, 0.0);
+    for (size_t i = 0; i < n; ++i) {
+        const double m = b->ctx[i]->opt.margin;
+        b->slack[i] = ext[2 * i] * m / (1.0 + m);
+    }
+    return SQ_OK;
+}
+
 int batch_layout(sq_batch *b) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -597,7 +663,11 @@ int batch_layout(sq_batch *b) {
     b->off_prm = take(n * sizeof(sq::BrentParams));
     b->off_state = take(n * sizeof(sq::BrentState));
     b->off_ext = take(2 * n * sizeof(double));
-    b->off_part = take(n * size_t(kReduceBlocks) * sizeof(double));
+    b->off_part = take(std::max<size_t>(n, 2) * size_t(kReduceBlocks) * sizeof(double));
+    size_t vtot = 0;
+    for (sq_ctx *c : b->ctx) vtot += size_t(c->nd);
+    b->off_vref = take(vtot * sizeof(double));
+    b->off_red = take(2 * n * sizeof(double));
     const size_t slot = size_t(b->nwg_cap) * size_t(b->max_ns) * sizeof(double);
     bool stream = false;
     for (const auto &g : b->groups) stream = stream || g.C > sq::kResidentCube;
@@ -966,6 +1036,7 @@ void sq_batch_default_options(sq_batch_options *opt) {
     opt->block_nodes = 0;
     opt->wg_per_cu = 0;
     opt->use_graph = 1;
+    opt->bounds_every = 1;
 }
 
 int sq_batch_create(sq_batch **out, sq_ctx *const *ctxs, int n, double *const *moments, double *const *rho,
@@ -978,7 +1049,9 @@ int sq_batch_create(sq_batch **out, sq_ctx *const *ctxs, int n, double *const *m
         auto b = std::unique_ptr<sq_batch>(new sq_batch());
         sq_batch_default_options(&b->opt);
         if (opt) b->opt = *opt;
-        if (b->opt.block_nodes < 0 || b->opt.wg_per_cu < 0) return fail(SQ_EINVAL, "invalid batch options");
+        if (b->opt.block_nodes < 0 || b->opt.wg_per_cu < 0 || b->opt.bounds_every < 0)
+            return fail(SQ_EINVAL, "invalid batch options");
+        if (b->opt.block_nodes > 0 && b->opt.block_nodes < 8) return fail(SQ_EINVAL, "block_nodes must be 0 or >= 8");
         for (int i = 0; i < n; ++i) {
             sq_ctx *c = ctxs[i];
             int rc = check_ctx(c, kBound);
@@ -1106,30 +1179,53 @@ int sq_batch_step(sq_batch *b, double *mu, double *energies, void *stream) {
         if (!rc) rc = hip_check(hipStreamWaitEvent(b->own, b->ev_in, 0), "ordering the batch");
         if (!rc) rc = upload_args(b, b->own);
         if (rc) return rc;
-        if (b->opt.use_graph) {
-            if (!b->exec) {
-                rc = hip_check(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal), "graph capture");
-                if (rc) return rc;
-                const int rc_pass = enqueue_pass(b, b->own);
-                hipGraph_t g = nullptr;
-                const int rc_end = hip_check(hipStreamEndCapture(b->own, &g), "graph capture");
+        // bounds on the first pass, every bounds_every passes, and whenever
+        // V_eff has moved too far for the previous ones
+        bool bounds = !b->have_bounds || b->opt.bounds_every <= 1 || b->passes % b->opt.bounds_every == 0;
+        if (!bounds) {
+            bool safe = false;
+            rc = reuse_is_safe(b, b->own, &safe);
+            if (rc) return rc;
+            bounds = !safe;
+        }
+        auto launch = [&](bool with_bounds) -> int {
+            const int g = with_bounds ? 1 : 0;
+            if (!b->opt.use_graph) return enqueue_pass(b, with_bounds, b->own);
+            if (!b->exec[g]) {
+                int r = hip_check(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal), "graph capture");
+                if (r) return r;
+                const int rc_pass = enqueue_pass(b, with_bounds, b->own);
+                hipGraph_t gr = nullptr;
+                const int rc_end = hip_check(hipStreamEndCapture(b->own, &gr), "graph capture");
                 if (rc_pass || rc_end) {
-                    if (g) (void)hipGraphDestroy(g);
+                    if (gr) (void)hipGraphDestroy(gr);
                     return rc_pass ? rc_pass : rc_end;
                 }
-                b->graph = g;
-                rc = hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiation");
-                if (rc) {
-                    drop_graph(b);
-                    return rc;
+                b->graph[g] = gr;
+                r = hip_check(hipGraphInstantiate(&b->exec[g], gr, nullptr, nullptr, 0), "graph instantiation");
+                if (r) {
+                    (void)hipGraphDestroy(gr);
+                    b->graph[g] = nullptr;
+                    b->exec[g] = nullptr;
+                    return r;
                 }
             }
-            rc = hip_check(hipGraphLaunch(b->exec, b->own), "graph launch");
-        } else {
-            rc = enqueue_pass(b, b->own);
-        }
+            return hip_check(hipGraphLaunch(b->exec[g], b->own), "graph launch");
+        };
+        rc = launch(bounds);
         if (rc) return rc;
         rc = finish_pass(b, b->own, mu, energies);
+        if (rc == SQ_EBOUNDS && !bounds) {
+            // reused bounds no longer enclose a spectrum: redo with fresh ones
+            bounds = true;
+            rc = launch(true);
+            if (!rc) rc = finish_pass(b, b->own, mu, energies);
+        }
+        if (!rc && bounds && b->opt.bounds_every > 1) rc = record_bounds(b, b->own);
+        if (!rc) {
+            ++b->passes;
+            b->have_bounds = true;
+        }
         const int rc2 = hip_check(hipEventRecord(b->ev_out, b->own), "ordering the batch");
         if (!rc2) (void)hipStreamWaitEvent(caller, b->ev_out, 0);
         return rc ? rc : rc2;

@@ -243,6 +243,9 @@ hipError_t launch_quadrature_weights(const double *mom, const double *ctab, doub
                                      long long nd, int npl, hipStream_t s);
 hipError_t launch_extent(const double *chi, const double *zeta, long long nd, double *partials,
                          int nblk, double *out, hipStream_t s);
+// out[0..1] = min, max of a - b over n entries (b may be null: of a).
+hipError_t launch_diff_extent(const double *a, const double *b, long long n, double *partials, int nblk,
+                              double *out, hipStream_t s);
 hipError_t launch_count(const double *W, const double *chi, const double *zeta, const double *rk,
                         long long nd, int nq, double mu, double kT, double *partials, int nblk,
                         double *out, hipStream_t s);

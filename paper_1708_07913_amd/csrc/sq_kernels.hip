@@ -1354,6 +1354,38 @@ __global__ __launch_bounds__(kRedBlock) void extent_kernel(const double *chi, co
     }
 }
 
+// min and max of a - b (b may be null: of a) per block, for extent_final.
+__global__ __launch_bounds__(kRedBlock) void diff_extent_kernel(const double *a, const double *b, long long n,
+                                                                double *partials) {
+    __shared__ double sh[kRedBlock / 64], sh2[kRedBlock / 64];
+    double lo = INFINITY, hi = -INFINITY;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double d = b ? a[i] - b[i] : a[i];
+        lo = fmin(lo, d);
+        hi = fmax(hi, d);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = lo;
+        sh2[w] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kRedBlock / 64; ++i) {
+            lo = fmin(lo, sh[i]);
+            hi = fmax(hi, sh2[i]);
+        }
+        partials[2 * blockIdx.x] = lo;
+        partials[2 * blockIdx.x + 1] = hi;
+    }
+}
+
 __global__ void extent_final(const double *partials, int nblk, double *out) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         double lo = INFINITY, hi = -INFINITY;
@@ -1626,6 +1658,13 @@ hipError_t launch_quadrature_weights(const double *mom, const double *ctab, doub
                                      int npl, hipStream_t s) {
     hipLaunchKernelGGL(weights_kernel, dim3(grid_for(nd * (npl + 1), 256)), dim3(256), 0, s, mom, ctab, W,
                        nd, npl);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_extent(const double *a, const double *b, long long n, double *partials, int nblk,
+                              double *out, hipStream_t s) {
+    hipLaunchKernelGGL(diff_extent_kernel, dim3(nblk), dim3(kRedBlock), 0, s, a, b, n, partials);
+    hipLaunchKernelGGL(extent_final, dim3(1), dim3(64), 0, s, partials, nblk, out);
     return hipGetLastError();
 }
 

@@ -170,3 +170,36 @@ def test_batch_ensemble_sampled():
         err = np.abs(r[nodes] - rho_ref).max() / r.max()
         print(f"    sampled rho rel err {err:.2e}", flush=True)
         assert err < 2e-5
+
+
+def test_batch_bounds_reuse_across_veff_update():
+    """bounds_every = 3: passes 2 and 3 reuse the first pass's bounds after a small
+    V_eff change; the result matches a fresh single-snapshot pass on those same
+    bounds, and a pass whose reused bounds are too tight is redone."""
+    sq = _sq()
+    wls = _small_ensemble()[:2]
+    print("case bounds reuse", flush=True)
+    snaps = _snaps(wls)
+    b = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=True, bounds_every=3)
+    b.step()
+    lo_hi = [g.spectral_bounds() for g in snaps]  # the bounds the batch just used
+    for g, wl in zip(snaps, wls):
+        g.update_veff(torch.from_numpy(0.98 * wl.veff()).cuda())
+    mu, e = b.step()  # reuses the first pass's bounds
+    for i, (g, wl) in enumerate(zip(snaps, wls)):
+        g.set_bounds(*lo_hi[i])
+        mom = g.moments()
+        mu1 = g.fermi_level(mom, wl.n_electrons)
+        rho1, e1 = g.density_energy(mom, mu1)
+        assert abs(mu[i] - mu1) < 1e-11
+        r = _np(b.rho[i])
+        assert np.abs(r - _np(rho1)).max() < 1e-12 * _np(rho1).max()
+        assert abs(e[i][3] - wl.n_electrons) < 1e-10 * wl.n_electrons
+    # a large change: the reused bounds no longer hold, the pass is redone
+    for g, wl in zip(snaps, wls):
+        g.update_veff(torch.from_numpy(3.0 * wl.veff()).cuda())
+    mu, e = b.step()
+    for i, (g, wl) in enumerate(zip(snaps, wls)):
+        mom1, mu1, rho1, e1 = g.scf_pass(wl.n_electrons)
+        assert abs(mu[i] - mu1) < 1e-11, (mu[i], mu1)
+        assert np.abs(_np(b.rho[i]) - _np(rho1)).max() < 1e-12 * _np(rho1).max()
