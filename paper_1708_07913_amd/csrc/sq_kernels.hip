@@ -665,7 +665,8 @@ template <int C, typename T>
 __device__ __forceinline__ double stencil_sum(const PlaneView<C, T> &pv, const T (&yrow)[2 * NO + Shape<C>::RB],
                                               const T (&tv)[C], int r, int z, const double (&kw)[NO + 1]) {
     constexpr int P = Shape<C>::P;
-    double acc = 0.0;
+    // two interleaved accumulators (odd and even d) halve the dependent FMA chain
+    double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int d = 1; d <= NO; ++d) {
         const T xs = pv.xr[r * P + NO + d] + pv.xr[r * P + NO - d];
@@ -673,9 +674,9 @@ __device__ __forceinline__ double stencil_sum(const PlaneView<C, T> &pv, const T
         T zs = T(0);
         if (z + d < C) zs = tv[z + d];
         if (z - d >= 0) zs = zs + tv[z - d];
-        acc += kw[d] * ((double)xs + (double)ys + (double)zs);
+        acc[d & 1] += kw[d] * ((double)xs + (double)ys + (double)zs);
     }
-    return acc;
+    return acc[1] + acc[0];
 }
 
 // Snapshot arguments and work items are read through the constant address
