@@ -33,6 +33,36 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
 
 
+FP64_VALU_TFLOPS = 78.6
+FLOPS_PER_POINT = 44  # 37-point stencil as pair sums, centre/V, -t^{k-1}
+
+
+def copy_bandwidth(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """HBM bandwidth of a device-to-device copy (bytes read + written per second),
+    median of `reps` copies timed with events on the current stream."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b) * 1e-3)
+    del src, dst
+    return 2.0 * nbytes / float(np.median(times))
+
+
+def stencil_roofline(bytes_, flops, seconds, bw):
+    """T_roof / T with T_roof = max(bytes / measured copy bandwidth, flops / FP64 VALU peak)."""
+    t_roof = max(bytes_ / bw, flops / (FP64_VALU_TFLOPS * 1e12))
+    return {"t_roof_s": t_roof, "t_s": seconds, "frac": t_roof / seconds,
+            "algorithmic_bytes": bytes_, "flops": flops}
+
+
 def workload(name):
     from paper_1708_07913_amd import workloads as W
     return {"paper": W.paper_size_cell, "paper-small": W.paper_cell_small, "large": W.large_cell,
@@ -134,6 +164,27 @@ def run_ensemble(args):
            "s_per_scf": wall / args.steps, "s_per_scf_reusing_bounds": reuse_s, "tiles": tiles,
            "autotune_s": tune_s,
            "electron_count_err_max": float(max(abs(e[i][3] - wl.n_electrons) for i, wl in enumerate(wls)))}
+    if prec == sq.FP32_MIXED:
+        # error of the mixed recurrence per snapshot, against the FP64 path on the
+        # same (FP64) bounds and at the batch's Fermi level
+        errs = []
+        for i, (wl, gm) in enumerate(zip(wls, snaps)):
+            g64 = sq.SQ.from_workload(wl, veff=torch.from_numpy(wl.veff()).cuda(), precision=sq.FP64)
+            lo, hi = g64.spectral_bounds()
+            mom64 = g64.moments()
+            gm.set_bounds(lo, hi)
+            rho64, e64 = g64.density_energy(mom64, float(mu[i]))
+            rhom, em = gm.density_energy(gm.moments(), float(mu[i]))
+            r64, rm = rho64.cpu().numpy(), rhom.cpu().numpy()
+            errs.append({"snapshot": wl.name, "rho_max_rel_err": float(np.abs(rm - r64).max() / r64.max()),
+                         "E_band_err_Ha_per_atom": float(abs(em[0] - e64[0]) / wl.natom),
+                         "F_err_Ha_per_atom": float(abs(em[2] - e64[2]) / wl.natom)})
+            print(f"[bench] {wl.name}: mixed rho err {errs[-1]['rho_max_rel_err']:.2e}", file=sys.stderr, flush=True)
+            del g64, mom64, rho64, rhom
+        rec["mixed_vs_fp64"] = {"rho_max_rel_err": max(x["rho_max_rel_err"] for x in errs),
+                                "E_band_err_Ha_per_atom": max(x["E_band_err_Ha_per_atom"] for x in errs),
+                                "F_err_Ha_per_atom": max(x["F_err_Ha_per_atom"] for x in errs),
+                                "per_snapshot": errs}
     print(json.dumps(rec), flush=True)
 
 
@@ -256,6 +307,14 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kname, wl.name),
             "kernel": kname, "algorithmic_bytes_per_launch": kbytes, "avg_launch_ms": kms}
 
+    bw = copy_bandwidth(torch)
+    flops_step = nd * ns * FLOPS_PER_POINT
+    roof_meas = {"bw_measured_GBs": bw / 1e9,
+                 "bw_source": "1 GiB device-to-device copy (read + write bytes), median of 5",
+                 "fp64_valu_peak_TFLOPs": FP64_VALU_TFLOPS,
+                 "lanczos": stencil_roofline(lanczos_bytes, 50 * flops_step, ph[0] * 1e-3, bw),
+                 "moments_fp64": stencil_roofline(moments_bytes, S * flops_step, ph[1] * 1e-3, bw)}
+
     rec = {"metric": METRIC, "value": value, "unit": "grid-pt*Chebyshev-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -270,6 +329,8 @@ def main():
            "moments_node_steps_per_s": nd * S / (ph[1] * 1e-3),
            "phase_ms": {"bounds": ph[0], "moments": ph[1], "fermi": ph[2], "density": ph[3]},
            "roofline": roof,
+           # the same kernels against the bandwidth a plain copy reaches on this GPU
+           "stencil_roofline_measured_bw": roof_meas,
            "electron_count": float(en[3]), "mu": mu}
 
     if not args.no_mixed:
@@ -289,6 +350,7 @@ def main():
                         "E_band_err_Ha_per_atom": float(abs(em[0] - e64[0]) / wl.natom),
                         "F_err_Ha_per_atom": float(abs(em[2] - e64[2]) / wl.natom),
                         "electron_count_err": float(abs(en_m[3] - wl.n_electrons))}
+        roof_meas["moments_mixed"] = stencil_roofline(moments_bytes // 2, S * flops_step, ph_m[1] * 1e-3, bw)
         print(f"[bench] mixed: {rec['mixed']['ms_per_step']:.1f} ms/step, rho err "
               f"{rec['mixed']['rho_max_rel_err_vs_fp64']:.2e}", file=sys.stderr, flush=True)
 

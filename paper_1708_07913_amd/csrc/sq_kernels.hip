@@ -661,20 +661,32 @@ __device__ __forceinline__ void load_yrows(const PlaneView<C, T> &pv, const T (&
 
 // Stencil part of (H t)[column r, plane z]: sum_d kw[d] (x pair + y pair + z
 // pair), x legs from the LDS plane, y legs from `yrow`, z legs from registers.
+// A register column value converted where it is used.  For FP32 columns the
+// empty asm hides the value from common-subexpression elimination, so the
+// compiler does not keep the widened copies of a column live across planes
+// (twice the registers of the column itself).
+__device__ __forceinline__ double widen_at_use(double v) { return v; }
+__device__ __forceinline__ double widen_at_use(float v) {
+    asm volatile("" : "+v"(v));
+    return (double)v;
+}
+
 template <int C, typename T>
 __device__ __forceinline__ double stencil_sum(const PlaneView<C, T> &pv, const T (&yrow)[2 * NO + Shape<C>::RB],
                                               const T (&tv)[C], int r, int z, const double (&kw)[NO + 1]) {
     constexpr int P = Shape<C>::P;
-    // two interleaved accumulators (odd and even d) halve the dependent FMA chain
+    // Every operand is widened before it is added: with FP32 storage the only
+    // rounding left in the step is the one of the stored vector.  Two
+    // interleaved accumulators (odd and even d) halve the dependent FMA chain.
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int d = 1; d <= NO; ++d) {
-        const T xs = pv.xr[r * P + NO + d] + pv.xr[r * P + NO - d];
-        const T ys = yrow[NO + r + d] + yrow[NO + r - d];
-        T zs = T(0);
-        if (z + d < C) zs = tv[z + d];
-        if (z - d >= 0) zs = zs + tv[z - d];
-        acc[d & 1] += kw[d] * ((double)xs + (double)ys + (double)zs);
+        const double xs = (double)pv.xr[r * P + NO + d] + (double)pv.xr[r * P + NO - d];
+        const double ys = (double)yrow[NO + r + d] + (double)yrow[NO + r - d];
+        double zs = 0.0;
+        if (z + d < C) zs = widen_at_use(tv[z + d]);
+        if (z - d >= 0) zs = zs + widen_at_use(tv[z - d]);
+        acc[d & 1] += kw[d] * (xs + ys + zs);
     }
     return acc[1] + acc[0];
 }
