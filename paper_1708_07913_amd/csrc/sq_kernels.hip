@@ -982,7 +982,22 @@ __device__ int sturm_count(int k, const double *a, const double *b, double x, do
     return cnt;
 }
 
-__device__ double sturm_bisect(int k, const double *a, const double *b, int target) {
+// Point idx (0..31) of the 32 interior points that split [lo, hi] into 33
+// equal parts; the same expression serves the lanes that evaluate the points
+// and the lanes that take them over as the new bracket.
+__device__ __forceinline__ double split_point(double lo, double hi, int idx) {
+    return lo + (hi - lo) * ((double)(idx + 1) / 33.0);
+}
+
+// Extreme eigenvalues of the tridiagonal T_k by Sturm counts, on one wave:
+// lanes 0-31 bracket the smallest eigenvalue (count target 1), lanes 32-63
+// the largest (target k).  A round evaluates the count at 32 interior points
+// of the bracket and keeps the sub-interval where it first reaches the
+// target, which narrows the bracket 33-fold where bisection halves it.  The
+// invariant count(lo) < target <= count(hi) holds throughout; the bracket
+// shrinks until no interior point is left (adjacent doubles) and its upper
+// end is returned, as with bisection.  out[0] = min, out[1] = max.
+__device__ void sturm_extremes(int k, const double *a, const double *b, double *out, int lane) {
     double lo = INFINITY, hi = -INFINITY, bmax2 = 0.0;
     for (int i = 0; i < k; ++i) {
         const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < k - 1 ? fabs(b[i]) : 0.0);
@@ -991,13 +1006,23 @@ __device__ double sturm_bisect(int k, const double *a, const double *b, int targ
         if (i < k - 1) bmax2 = fmax(bmax2, b[i] * b[i]);
     }
     const double pivmin = 2.2250738585072014e-308 * fmax(bmax2, 1.0);
-    for (int it = 0; it < 256; ++it) {
-        const double mid = lo + 0.5 * (hi - lo);
-        if (mid <= lo || mid >= hi) break;
-        if (sturm_count(k, a, b, mid, pivmin) >= target) hi = mid;
-        else lo = mid;
+    const int half = lane >> 5, j = lane & 31;
+    const int target = half ? k : 1;
+    for (int round = 0; round < 64; ++round) {
+        const double x = split_point(lo, hi, j);
+        const bool inside = (x > lo) & (x < hi);
+        const unsigned long long in_mask = __builtin_amdgcn_ballot_w64(inside);
+        if ((unsigned)(half ? in_mask >> 32 : in_mask) == 0u) break;  // uniform per half
+        const bool ge = inside ? sturm_count(k, a, b, x, pivmin) >= target : x >= hi;
+        const unsigned long long gm = __builtin_amdgcn_ballot_w64(ge);
+        const unsigned g32 = (unsigned)(half ? gm >> 32 : gm);
+        const int f = g32 ? __builtin_ctz(g32) : 32;  // first point with count >= target
+        const double nlo = f > 0 ? split_point(lo, hi, f - 1) : lo;
+        const double nhi = f < 32 ? split_point(lo, hi, f) : hi;
+        lo = nlo;
+        hi = nhi;
     }
-    return hi;
+    if (j == 0) out[half] = hi;
 }
 
 // Resident cubes keep v_j in registers; the sweep writes v_j to the slot (it
@@ -1258,7 +1283,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
             __syncthreads();
         }
         __syncthreads();
-        if (tid < 2) L.bc[tid] = sturm_bisect(ksteps, LL.al, LL.be, tid == 0 ? 1 : ksteps);
+        if (tid < 64) sturm_extremes(ksteps, LL.al, LL.be, L.bc, tid);
         __syncthreads();
         if (tid == 0) {
             const double lmn = L.bc[0], lmx = L.bc[1];

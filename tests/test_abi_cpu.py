@@ -105,3 +105,16 @@ def test_null_context_calls():
     assert lib.sq_spectral_bounds(None, None, None, None) == -1
     assert lib.sq_query(None, None, None, None, None) == -1
     lib.sq_destroy(None)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU: --gpus above 1 exits with a message."""
+    import json
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
