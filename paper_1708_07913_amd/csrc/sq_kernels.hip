@@ -30,10 +30,13 @@ namespace {
 
 constexpr int NO = kNoMax;
 
-// Rows of the cube owned by one thread: one column for small regions, two
-// y-adjacent columns from 19 points (512-thread workgroups, 256 VGPRs per
-// lane; the pair shares its y-neighbour reads), three beyond 31 points.
-constexpr int rows_per_thread(int C) { return C > kResidentCube ? 3 : (C >= 19 ? 2 : 1); }
+// Rows of the cube owned by one thread: one column up to 27 points (a
+// workgroup of C^2 threads, two or more waves per SIMD), two y-adjacent
+// columns for 29 and 31 points (512-thread workgroups, 256 VGPRs per lane; the
+// pair shares its y-neighbour reads), three beyond 31 points.  Two rows on the
+// 21-27-point cubes leave one wave per SIMD and run 12-31 % slower; one row
+// on 29 points spills.
+constexpr int rows_per_thread(int C) { return C > kResidentCube ? 3 : (C >= 29 ? 2 : 1); }
 
 template <int C>
 struct Shape {
