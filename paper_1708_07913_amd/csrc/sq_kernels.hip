@@ -17,8 +17,10 @@
 //     added into LDS at the run's end;
 //   * workgroups walk node ranges split by XCD (blockIdx % 8) so that one
 //     XCD's L2 holds neighbouring V_eff windows and projector tables.
-// FP32-mixed: vectors, LDS plane, potential window and stencil pair sums in
-// FP32; every accumulation (stencil sum, projector terms, update, dots) FP64.
+// FP32-mixed: vectors, LDS plane and potential window stored in FP32; every
+// operand is widened to FP64 before it is used, so the arithmetic (stencil
+// sum, projector terms, update, dots) is FP64 and the one rounding per step
+// is the FP32 store of t^{k+1}.
 #include <hip/hip_runtime.h>
 
 #include "sq_internal.h"
@@ -970,7 +972,8 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
 // ---------------------------------------------------------------------------
 // Lanczos spectral bounds (Sec. 3.2): Paige's ordering of the three-term
 // recurrence from a fixed SplitMix64 start vector, no reorthogonalisation,
-// extreme eigenvalues of the tridiagonal by Sturm bisection.
+// extreme eigenvalues of the tridiagonal by Sturm counts (a 32-point
+// multisection that ends on the bracket bisection reaches).
 // ---------------------------------------------------------------------------
 __device__ int sturm_count(int k, const double *a, const double *b, double x, double pivmin) {
     int cnt = 0;
