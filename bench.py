@@ -30,7 +30,14 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1708_07913_amd", "csrc", "sq_kernels.h
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    """Hash of the kernel code with comments and whitespace removed, so that a
+    comment edit keeps the recorded counter traffic valid."""
+    import re
+    text = open(KERNEL_SOURCE).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = " ".join(text.split())
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 FP64_VALU_TFLOPS = 78.6
