@@ -40,6 +40,15 @@ constexpr int NO = kNoMax;
 // on 29 points spills.
 constexpr int rows_per_thread(int C) { return C > kResidentCube ? 3 : (C >= 29 ? 2 : 1); }
 
+// Smallest row stride >= pe for which a step from (x = xw - 1, y) to
+// (x = 0, y + rb) moves the address by 1 modulo 32 (see Shape::P).
+constexpr int plane_stride(int c, int rb, int xw, int pe) {
+    if (xw == 32) return pe;
+    for (int p = pe; p < pe + 32; ++p)
+        if (((rb * p - xw) % 32 + 32) % 32 == 0) return p;
+    return pe;  // no such stride (even rb with odd xw): keep the plain layout
+}
+
 template <int C>
 struct Shape {
     static constexpr int RB = rows_per_thread(C);
@@ -50,9 +59,15 @@ struct Shape {
     // the 64-bit LDS reads free of bank conflicts
     static constexpr int XW = (C == 29 || C == 31) ? 32 : C;  // threads per row group
     static constexpr int NT = XW * YP;                       // threads owning row groups
-    static constexpr int P = C + 2 * NO;                     // padded plane edge (zero halo NO)
+    static constexpr int PE = C + 2 * NO;                    // padded plane edge (zero halo NO)
+    // Row stride of the plane.  With XW = C the lanes of a wave run along x
+    // and step to the next row group at x = C; a stride with
+    // RB * P = XW (mod 32) makes that step advance the 8-byte address by one,
+    // so any 32 consecutive lanes touch 32 distinct bank pairs for every
+    // uniform (dx, dy) offset.  The 32-lane row groups need no padding.
+    static constexpr int P = plane_stride(C, RB, XW, PE);
     // + RB + 1 rows read (and discarded) by columns past the cube edge
-    static constexpr int ROWS = P + RB + 1;
+    static constexpr int ROWS = PE + RB + 1;
     static constexpr int PLANE = ROWS * P + 1;               // + one write-only cell for idle threads
     static constexpr int IDLE_CORNER = 0;                    // idle threads read real cells and discard them
     static constexpr int IDLE_WRITE = ROWS * P;
