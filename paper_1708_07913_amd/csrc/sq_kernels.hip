@@ -33,7 +33,7 @@ namespace {
 constexpr int NO = kNoMax;
 
 // Rows of the cube owned by one thread: one column up to 27 points (a
-// workgroup of C^2 threads, two or more waves per SIMD), two y-adjacent
+// workgroup of C^2 threads, 7-12 waves for 21-27 points), two y-adjacent
 // columns for 29 and 31 points (512-thread workgroups, 256 VGPRs per lane; the
 // pair shares its y-neighbour reads), three beyond 31 points.  Two rows on the
 // 21-27-point cubes leave one wave per SIMD and run 12-31 % slower; one row
@@ -41,7 +41,8 @@ constexpr int NO = kNoMax;
 constexpr int rows_per_thread(int C) { return C > kResidentCube ? 3 : (C >= 29 ? 2 : 1); }
 
 // Smallest row stride >= pe for which a step from (x = xw - 1, y) to
-// (x = 0, y + rb) moves the address by 1 modulo 32 (see Shape::P).
+// (x = 0, y + rb) moves the address by 1 modulo 32 (see Shape::P); the cube
+// side c is not needed beyond xw and pe.
 constexpr int plane_stride(int c, int rb, int xw, int pe) {
     if (xw == 32) return pe;
     for (int p = pe; p < pe + 32; ++p)
