@@ -462,6 +462,7 @@ struct Chain2 {
     int vb, nvb;       // their value bases
     double acc;
     double pv[2];      // values of planes z and z + 1 (indexed by plane parity)
+    double c;          // per-image coefficient of the current record (second Lanczos pass)
 
     __device__ __forceinline__ int sl() const { return (int)(rx & 0xFFu); }
     __device__ __forceinline__ int z1() const { return (int)((rx >> 16) & 0xFFu); }
@@ -1232,12 +1233,18 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
             double db = 0.0;
             Chain2 ch[RB][NCH];
 #pragma unroll
-            for (int r = 0; r < RB; ++r) chains2_start(L, pvr, Cols<C>::column(r), ch[r], nch);
-            double un[2][RB], xn[2][RB];
+            for (int r = 0; r < RB; ++r) {
+                chains2_start(L, pvr, Cols<C>::column(r), ch[r], nch);
+#pragma unroll
+                for (int ci = 0; ci < NCH; ++ci) ch[r][ci].c = L.cs[ch[r][ci].sl()];
+            }
+            // u (and, streamed, v_j) loads run LA planes ahead
+            constexpr int LA = 3;
+            double un[LA][RB], xn[LA][RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
 #pragma unroll
-                for (int z = 0; z < 2; ++z) {
+                for (int z = 0; z < LA; ++z) {
                     un[z][r] = z < C ? bload<double>(wlr, voff[r], (unsigned)(z * S::CC) * 8u) : 0.0;
                     xn[z][r] = 0.0;
                     if (kStream && z < C) xn[z][r] = bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u);
@@ -1247,16 +1254,16 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
             for (int z = 0; z < C; ++z) {
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    double uz = un[z & 1][r];
-                    const double vj = scx * (kStream ? xn[z & 1][r] : tv[r][z]);
-                    if (z + 2 < C) {
-                        const unsigned sz2 = (unsigned)((z + 2) * S::CC) * 8u;
-                        un[z & 1][r] = bload<double>(wlr, voff[r], sz2);
-                        if (kStream) xn[z & 1][r] = bload<double>(slr, voff[r], sz2);
+                    double uz = un[z % LA][r];
+                    const double vj = scx * (kStream ? xn[z % LA][r] : tv[r][z]);
+                    if (z + LA < C) {
+                        const unsigned sz2 = (unsigned)((z + LA) * S::CC) * 8u;
+                        un[z % LA][r] = bload<double>(wlr, voff[r], sz2);
+                        if (kStream) xn[z % LA][r] = bload<double>(slr, voff[r], sz2);
                     }
 #pragma unroll
                     for (int ci = 0; ci < NCH; ++ci)
-                        if (ci == 0 || ci < nch) uz += L.cs[ch[r][ci].sl()] * ch[r][ci].pv[z & 1];
+                        if (ci == 0 || ci < nch) uz += ch[r][ci].c * ch[r][ci].pv[z & 1];
                     double w = uz - alpha * vj;
                     if (!cl.valid(r)) w = 0.0;
                     if (kStream) bstore(w, sly, voff[r], (unsigned)(z * S::CC) * 8u);
@@ -1270,7 +1277,15 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
                             pin(ch[r][ci].acc);
                         }
                     }
+                    // a run that ends here hands over to the next record: its
+                    // coefficient is read once per run instead of once per plane
+                    bool sw[NCH];
+#pragma unroll
+                    for (int ci = 0; ci < NCH; ++ci) sw[ci] = z == ch[r][ci].z1();
                     chains2_advance<C, NCH>(ch[r], L.s[cur ^ 1], L.runs, pvr, z, nch);
+#pragma unroll
+                    for (int ci = 0; ci < NCH; ++ci)
+                        if ((ci == 0 || ci < nch) && sw[ci]) ch[r][ci].c = L.cs[ch[r][ci].sl()];
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
