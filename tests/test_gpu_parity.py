@@ -201,6 +201,22 @@ def test_large_cell_sampled():
 # Regions wider than 31 points stream the current vector through the
 # workgroup's buffers (three columns per thread); the cube is larger than the
 # 16^3 cell here, so it wraps the periodic cell twice.
+ONE_COLUMN = {
+    # one cube column per thread with a padded plane stride; name: (rcut, npl, seed)
+    "one_column_cube23": (5.5, 16, 21),
+    "one_column_cube25": (6.0, 12, 22),
+    "one_column_cube27": (6.5, 16, 23),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ONE_COLUMN))
+def test_one_column_cubes_sampled(name):
+    rc, npl, seed = ONE_COLUMN[name]
+    wl = W.fcc_workload(name, 1, 8.0, 0.1, seed, 0.5, rc, npl, 1.0)
+    print(f"case {name} n={wl.n} C={2 * int(rc / wl.h_eff + 0.5) + 1}", flush=True)
+    _sampled_parity(wl, 6, seed=seed)
+
+
 STREAMED = {
     # name: (rcut, npl, seed)
     "streamed_cube33": (8.0, 16, 11),
