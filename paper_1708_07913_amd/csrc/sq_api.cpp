@@ -835,7 +835,7 @@ int sq_setup(sq_ctx **ctx, double cell, double h, int fd_order, double rcut, int
                 return fail(SQ_ECAPACITY, "more than four projector spheres overlap at a grid point");
             if (c->max_overlap > 2 && c->C > sq::kResidentCube)
                 return fail(SQ_ECAPACITY, "regions wider than 31 points support at most two overlapping projector spheres");
-            c->nch = c->max_overlap > 2 ? 4 : 2;
+            c->nch = c->max_overlap > 2 ? 4 : (c->max_overlap > 1 ? 2 : 1);
         }
         // discrete-orthogonality table on N_q = n_pl + 1 Chebyshev-Gauss nodes
         c->ctab.assign(size_t(c->nq) * c->nq, 0.0);

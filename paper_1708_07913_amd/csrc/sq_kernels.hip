@@ -27,6 +27,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace sq {
 namespace {
 
@@ -1334,6 +1336,663 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register-ring recurrence kernels (cubes whose columns stay in registers).
+//
+// A thread keeps NR = C + NO + 1 plane slots per owned column.  A sweep reads
+// its input vector at ring[z + IN] and writes its output vector at
+// ring[z + OUT]: upward sweeps (z = 0 .. C-1) have IN = NO + 1, OUT = 0 and
+// downward sweeps the reverse.  The stencil at plane z reaches planes z +- NO,
+// so the input plane z - (NO + 1) (upward) held in slot z is dead when the
+// output of plane z is written there.  Consecutive steps alternate direction
+// and the input of one step is the output of the previous one, so one column
+// of slots (instead of one per vector) carries the recurrence.
+// ---------------------------------------------------------------------------
+template <bool UP> struct RingDir {
+    static constexpr int IN = UP ? NO + 1 : 0;
+    static constexpr int OUT = UP ? 0 : NO + 1;
+    // plane of loop iteration i
+    static constexpr __host__ __device__ int plane(int i, int C) { return UP ? i : C - 1 - i; }
+};
+
+// One chain of disjoint z-runs walked upward (first record first) or
+// downward (last record first).  The sentinel record never becomes active
+// and never ends in either direction.
+template <bool UP>
+struct ChainD {
+    int i, b, e;    // current record, chain range [b, e)
+    unsigned rx;    // slot | z_first << 8 | z_last << 16
+    int vb;         // value base of the current record
+    double acc;
+    double pv;      // projector value at the plane being processed
+
+    __device__ __forceinline__ int sl() const { return (int)(rx & 0xFFu); }
+    __device__ __forceinline__ int z0() const { return (int)((rx >> 8) & 0xFFu); }
+    __device__ __forceinline__ int z1() const { return (int)((rx >> 16) & 0xFFu); }
+    __device__ __forceinline__ void load(const uint2 *runs, int sentinel) {
+        const bool in = UP ? i < e : i >= b;
+        const uint2 r = runs[in ? i : sentinel];
+        rx = r.x;
+        vb = (int)r.y;
+    }
+    __device__ __forceinline__ void start(const uint2 *runs, int b0, int e0, int sentinel) {
+        b = b0;
+        e = e0;
+        i = UP ? b0 : e0 - 1;
+        acc = 0.0;
+        pv = 0.0;
+        load(runs, sentinel);
+    }
+    __device__ __forceinline__ void fetch(__amdgpu_buffer_rsrc_t pvr, int z) {
+        const bool act = (z >= z0()) & (z <= z1());
+        pv = bload<double>(pvr, act ? (unsigned)(vb + z) * 8u : kIdleOffset, 0u);
+    }
+    // after plane z: a run that ends here adds its dot product into s[slot]
+    __device__ __forceinline__ void finish(double *s, int z, const uint2 *runs, int sentinel) {
+        if (z == (UP ? z1() : z0())) {
+            atomicAdd(&s[sl()], acc);
+            acc = 0.0;
+            i += UP ? 1 : -1;
+            load(runs, sentinel);
+        }
+    }
+};
+
+template <bool UP, int C, typename T, int NCH>
+__device__ __forceinline__ void chainsd_start(const Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr, int column,
+                                              ChainD<UP> (&ch)[NCH], int nch) {
+    constexpr int SENT = Shape<C>::MAXRUNS;
+    const bool ok = column >= 0;
+    const int b = ok ? L.col_start[column] : 0;
+    const int e = ok ? L.col_start[column + 1] : 0;
+#pragma unroll
+    for (int ci = 0; ci < NCH; ++ci) {
+        const int s0 = b + (ok ? L.col_off[column][ci] : 0);
+        const int s1 = ci + 1 < NCH ? b + (ok ? L.col_off[column][ci + 1] : 0) : e;
+        ch[ci].start(L.runs, s0, s1, SENT);
+        if (ci == 0 || ci < nch) ch[ci].fetch(pvr, UP ? 0 : C - 1);
+    }
+}
+
+// After plane z: close finished runs into s_dst and fetch the next plane.
+template <bool UP, int C, int NCH>
+__device__ __forceinline__ void chainsd_advance(ChainD<UP> (&ch)[NCH], double *s_dst, const uint2 *runs,
+                                                __amdgpu_buffer_rsrc_t pvr, int z, int nch) {
+#pragma unroll
+    for (int ci = 0; ci < NCH; ++ci) {
+        if (ci == 0 || ci < nch) {
+            ch[ci].finish(s_dst, z, runs, Shape<C>::MAXRUNS);
+            const int zn = UP ? z + 1 : z - 1;
+            if (zn >= 0 && zn < C) ch[ci].fetch(pvr, zn);
+        }
+    }
+}
+
+// Sum of four values over the workgroup, returned to every thread.
+template <int C, typename T, int NCH>
+__device__ __forceinline__ void block_sum4(Lds<C, T, NCH> &L, double (&v)[4], int tid) {
+    constexpr int NW = Shape<C>::NW;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+    const int w = tid >> 6;
+    __syncthreads();
+    // red holds two doubles per wave: two rounds of two values
+    if ((tid & 63) == 0) {
+        L.red[2 * w] = v[0];
+        L.red[2 * w + 1] = v[1];
+    }
+    __syncthreads();
+    if (tid < 2) {
+        double s = 0.0;
+        for (int i = 0; i < NW; ++i) s += L.red[2 * i + tid];
+        L.bc[tid] = s;
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) {
+        L.red[2 * w] = v[2];
+        L.red[2 * w + 1] = v[3];
+    }
+    __syncthreads();
+    if (tid < 2) {
+        double s = 0.0;
+        for (int i = 0; i < NW; ++i) s += L.red[2 * i + tid];
+        L.bc[2 + tid] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = uniform(L.bc[i]);
+    __syncthreads();
+}
+
+// y legs of plane z for all RB columns, own rows from the ring.
+template <int C, int IN>
+__device__ __forceinline__ void load_yrows_ring(const PlaneView<C, double> &pv,
+                                                const double (&R)[Shape<C>::RB][C + NO + 1], int z,
+                                                double (&yrow)[2 * NO + Shape<C>::RB]) {
+    constexpr int P = Shape<C>::P, RB = Shape<C>::RB;
+#pragma unroll
+    for (int j = 0; j < NO; ++j) yrow[j] = pv.ylo[j * P];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) yrow[NO + r] = R[r][z + IN];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) yrow[NO + RB + j] = pv.yhi[j * P];
+}
+
+// Stencil part of (H x)[column r, plane z] with the column's planes in the ring
+// at offset IN: sum_d kw[d] (x pair + y pair + z pair).
+template <int C, int IN>
+__device__ __forceinline__ double stencil_ring(const PlaneView<C, double> &pv, const double (&yrow)[2 * NO + Shape<C>::RB],
+                                               const double (&col)[C + NO + 1], int r, int z,
+                                               const double (&kw)[NO + 1]) {
+    constexpr int P = Shape<C>::P;
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int d = 1; d <= NO; ++d) {
+        const double xs = pv.xr[r * P + NO + d] + pv.xr[r * P + NO - d];
+        const double ys = yrow[NO + r + d] + yrow[NO + r - d];
+        double zs = 0.0;
+        if (z + d < C) zs = col[z + d + IN];
+        if (z - d >= 0) zs = zs + col[z - d + IN];
+        acc[d & 1] += kw[d] * (xs + ys + zs);
+    }
+    return acc[1] + acc[0];
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Chebyshev moments on the register ring (Sec. 3.2 recurrence and
+// moments).  Per step: t^k in the ring (input layout), t^{k-1} read from the
+// workgroup's slot plane by plane and replaced there by t^k, t^{k+1} into the
+// ring (output layout): two vector transfers per step.
+// ---------------------------------------------------------------------------
+struct MomentsStep {
+    double al, invz, c0;
+    int k;
+    bool prev;  // t^{k-1} is read from the slot (k > 0)
+};
+
+template <int C, int NCH, bool UP, typename AT>
+__device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, NCH> &L, const Cols<C> &cl,
+                                                   double (&R)[Shape<C>::RB][C + NO + 1],
+                                                   __amdgpu_buffer_rsrc_t slr, __amdgpu_buffer_rsrc_t vr,
+                                                   __amdgpu_buffer_rsrc_t pvr, const unsigned (&vcol)[Shape<C>::RB],
+                                                   const unsigned (&voff)[Shape<C>::RB], unsigned zbase,
+                                                   const double (&kw)[NO + 1], const MomentsStep &st,
+                                                   double *snext, int nch, int centre_r, double *mrow,
+                                                   double &d1, double &d2) {
+    using S = Shape<C>;
+    using D = RingDir<UP>;
+    constexpr int RB = S::RB;
+    constexpr int MC = (C - 1) / 2;
+    const int n = A.n;
+    ChainD<UP> ch[RB][NCH];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) chainsd_start<UP>(L, pvr, Cols<C>::column(r), ch[r], nch);
+    unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
+    asm volatile("" : "+s"(zb));
+    double vzn[RB], tpn[RB];
+    {
+        constexpr int z = D::plane(0, C);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)z) % (unsigned)n) * 8u);
+            tpn[r] = st.prev ? bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u) : 0.0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        const int z = D::plane(i, C);
+        const unsigned sz = (unsigned)(z * S::CC) * 8u;
+        double vz[RB], tprev[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            vz[r] = vzn[r];
+            tprev[r] = tpn[r];
+            if (i + 1 < C) {
+                const int zn = D::plane(i + 1, C);
+                vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)zn) % (unsigned)n) * 8u);
+                if (st.prev) tpn[r] = bload<double>(slr, voff[r], (unsigned)(zn * S::CC) * 8u);
+            }
+            L.plane[i & 1][cl.pcw[r]] = R[r][z + D::IN];
+        }
+        __syncthreads();
+        const PlaneView<C, double> pv(L.plane[0], i & 1, cl.corner);
+        double yrow[2 * NO + RB];
+        load_yrows_ring<C, D::IN>(pv, R, z, yrow);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const double acc = stencil_ring<C, D::IN>(pv, yrow, R[r], r, z, kw);
+            const double tz = R[r][z + D::IN];
+            const double u = acc + (vz[r] + st.c0) * st.invz * tz;
+            double pval[NCH];
+            double nvd = st.al * u - tprev[r];
+#pragma unroll
+            for (int ci = 0; ci < NCH; ++ci) {
+                pval[ci] = 0.0;
+                if (ci == 0 || ci < nch) {
+                    pval[ci] = ch[r][ci].pv;
+                    nvd += L.cs[ch[r][ci].sl()] * pval[ci];
+                }
+            }
+            if (!cl.valid(r)) nvd = 0.0;
+            R[r][z + D::OUT] = nvd;
+            bstore(tz, slr, voff[r], sz);  // t^k over t^{k-1}
+            d1 += nvd * nvd;
+            d2 += nvd * tz;
+            pin(d1);
+            pin(d2);
+#pragma unroll
+            for (int ci = 0; ci < NCH; ++ci) {
+                if (ci == 0 || ci < nch) {
+                    ch[r][ci].acc += pval[ci] * nvd;
+                    pin(ch[r][ci].acc);
+                }
+            }
+            chainsd_advance<UP, C, NCH>(ch[r], snext, L.runs, pvr, z, nch);
+            if (z == MC && centre_r == r) {
+                mrow[st.k + 1] = nvd;
+                if (st.k == 0) L.bc[2] = nvd;
+                if (fabs(nvd) > 1.0 + A.bounds_tol) atomicOr(A.flags, kFlagBounds);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+}
+
+template <int C, int NCH>
+__global__ __launch_bounds__(Shape<C>::BLOCK) void moments_ring_kernel(LaunchArgs K) {
+    using S = Shape<C>;
+    constexpr int RB = S::RB;
+    constexpr int MC = (C - 1) / 2;
+    constexpr int NR = C + NO + 1;
+    static_assert(!S::STREAM, "register ring: resident cubes only");
+    __shared__ Lds<C, double, NCH> L;
+    const int tid = threadIdx.x;
+    Cols<C> cl;
+    cl.init(tid);
+    int centre_r = -1;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (cl.col[r] == MC * C + MC) centre_r = r;
+    const long long slot_bytes = K.slot_elems * 8;
+    const __amdgpu_buffer_rsrc_t slr =
+        make_rsrc(reinterpret_cast<double *>(K.slots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
+    unsigned voff[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * 8u : kIdleOffset;
+
+    WorkSource work;
+    SnapPtr Ap;
+    long long qfirst, qend, qstep;
+    while (work.next(K, L, tid, Ap, qfirst, qend, qstep)) {
+    const auto &A = *Ap;
+    const int n = A.n;
+    const int npl = A.npl, half = npl / 2;
+    const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
+    const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
+    const double kin0 = -3.0 * A.w[0];
+
+    for (long long q = qfirst; q < qend; q += qstep) {
+        int qi, qj, qk;
+        node_coords(q, n, qi, qj, qk);
+        setup_region(A, L, qi, qj, qk, tid);
+        const int ni = L.ni < kMaxImages ? L.ni : kMaxImages;
+        const int nch = L.nch;
+        const unsigned zbase = (unsigned)pmod(qk - A.m, n);
+        const double chi = uniform(A.chi[q]), zeta = uniform(A.zeta[q]);
+        const double invz = uniform(1.0 / zeta);
+        double kw[NO + 1];
+        kw[0] = 0.0;
+#pragma unroll
+        for (int d = 1; d <= NO; ++d) kw[d] = uniform(-0.5 * A.w[d] * invz);
+        unsigned vcol[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            vcol[r] = cl.valid(r) ? (unsigned)(pmod(qi - A.m + cl.x, n) + n * pmod(qj - A.m + cl.y0 + r, n)) * 8u
+                                  : kIdleOffset;
+        double *mrow = A.moments + q * (long long)(npl + 1);
+        // t^0 = e_q in the upward sweep's input layout
+        double R[RB][NR];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const int z = i - (NO + 1);
+                R[r][i] = (z >= 0 && centre_r == r && z == MC) ? 1.0 : 0.0;
+            }
+        if (tid == 0) mrow[0] = 1.0;
+        int cur = 0;
+        projector_dots<false>(L, pvr, cl, cur, nch, [&](int r, int z) {
+            return (centre_r == r && z == MC) ? 1.0 : 0.0;
+        });
+        MomentsStep st;
+        st.invz = invz;
+        st.c0 = uniform(kin0 - chi);
+        // one step; the ring layout alternates, so steps are taken in (up, down)
+        // pairs and every pass of the loop starts in the upward layout
+        auto step = [&](int k, auto up) {
+            constexpr bool UP = decltype(up)::value;
+            st.al = k == 0 ? 1.0 : 2.0;
+            st.k = k;
+            st.prev = k > 0;
+            const double scale = uniform(st.al * invz);
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK)
+                L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur][i] : 0.0;
+            __syncthreads();
+            double d1 = 0.0, d2 = 0.0;
+            moments_ring_sweep<C, NCH, UP>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st, L.s[cur ^ 1], nch,
+                                           centre_r, mrow, d1, d2);
+            block_sum2(L, d1, d2, tid);
+            if (k + 1 > half / 2) {
+                if (tid == 0) {
+                    const double r2k = 2.0 * d1 - 1.0, r2k1 = 2.0 * d2 - L.bc[2];
+                    mrow[2 * (k + 1)] = r2k;
+                    mrow[2 * (k + 1) - 1] = r2k1;
+                    if (fabs(r2k) > 1.0 + A.bounds_tol || fabs(r2k1) > 1.0 + A.bounds_tol)
+                        atomicOr(A.flags, kFlagBounds);
+                }
+            }
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) L.s[cur][i] = 0.0;
+            cur ^= 1;
+            __syncthreads();
+        };
+        // n_pl is a multiple of 4: the number of steps, n_pl / 2, is even
+        for (int k = 0; k < half; k += 2) {
+            step(k, std::true_type());
+            step(k + 1, std::false_type());
+        }
+    }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos bounds on the register ring, one pass per step (Sec. 3.2; Paige's
+// ordering up to rounding).  x_j denotes w_{j-1} = beta_{j-1} v_j, kept
+// unnormalised (x_0 = v_0, the start vector); sigma_j = 1 / beta_{j-1}.
+// Sweep j:
+//   * forms x_j plane by plane NO planes ahead of the stencil, in the ring:
+//       x_j = sigma_{j-1} (U_{j-1} + sum_I c_I s_I(x_{j-1}) p_I)
+//             - beta_{j-2} sigma_{j-2} x_{j-2} - alpha_{j-1} sigma_{j-1} x_{j-1}
+//     with U_{j-1} = L x_{j-1} the local (stencil + potential) part from the
+//     previous sweep, x_{j-1} and x_{j-2} read from the two workgroup slots;
+//     x_j is written over x_{j-2}; the same walk over the projector runs adds
+//     the projector term and accumulates s_I(x_j) = p_I . x_j;
+//   * applies the local part: U_j = L x_j into the ring's output layout.
+// After the sweep: beta_{j-1} = |x_j|,
+//   alpha_j = sigma_j^2 (x_j . U_j + sum_I c_I s_I(x_j)^2) - sigma_{j-1} x_{j-1} . x_j,
+// which is u_j . v_j with u_j = H v_j - beta_{j-1} v_{j-1}.
+// Three vector transfers per step (read x_{j-1}, x_{j-2}; write x_j).
+// ---------------------------------------------------------------------------
+struct LanczosStep {
+    int j;
+    double fu, fa, fb;  // formation coefficients of U_{j-1} (+ projector part), x_{j-1}, x_{j-2}
+    bool ra, rb;        // x_{j-1} / x_{j-2} are read
+};
+
+template <int C, int NCH, bool UP, typename AT>
+__device__ __forceinline__ void lanczos_ring_sweep(const AT &A, Lds<C, double, NCH> &L, const Cols<C> &cl,
+                                                   double (&R)[Shape<C>::RB][C + NO + 1],
+                                                   __amdgpu_buffer_rsrc_t rda, __amdgpu_buffer_rsrc_t rdb,
+                                                   __amdgpu_buffer_rsrc_t vr, __amdgpu_buffer_rsrc_t pvr,
+                                                   const unsigned (&vcol)[Shape<C>::RB],
+                                                   const unsigned (&voff)[Shape<C>::RB], unsigned zbase,
+                                                   const double (&kw)[NO + 1], double kin0, const LanczosStep &st,
+                                                   double *snext, int nch, double (&dots)[4]) {
+    using S = Shape<C>;
+    using D = RingDir<UP>;
+    constexpr int RB = S::RB;
+    constexpr int FA = 1;  // slot reads run FA planes ahead of the formation
+    const int n = A.n;
+    ChainD<UP> ch[RB][NCH];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) chainsd_start<UP>(L, pvr, Cols<C>::column(r), ch[r], nch);
+    unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
+    asm volatile("" : "+s"(zb));
+    // slots not yet written in this node are not read (their loads return 0)
+    unsigned aoff[RB], boff[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        aoff[r] = st.ra ? voff[r] : kIdleOffset;
+        boff[r] = st.rb ? voff[r] : kIdleOffset;
+    }
+    double an[FA][RB], bn[FA][RB];
+#pragma unroll
+    for (int f = 0; f < FA; ++f)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            an[f][r] = 0.0;
+            bn[f][r] = 0.0;
+            if (f < C) {
+                const unsigned so = (unsigned)(D::plane(f, C) * S::CC) * 8u;
+                an[f][r] = bload<double>(rda, aoff[r], so);
+                bn[f][r] = bload<double>(rdb, boff[r], so);
+            }
+        }
+    double da = 0.0, db = 0.0, de = 0.0;
+    // formation of plane D::plane(f): x into the ring's input layout and the slot
+    auto form = [&](int f) {
+        const int z = D::plane(f, C);
+        const unsigned sz = (unsigned)(z * S::CC) * 8u;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const double a = an[f % FA][r], b = bn[f % FA][r];
+            if (f + FA < C) {
+                const unsigned so = (unsigned)(D::plane(f + FA, C) * S::CC) * 8u;
+                an[f % FA][r] = bload<double>(rda, aoff[r], so);
+                bn[f % FA][r] = bload<double>(rdb, boff[r], so);
+            }
+            // step 0: fu = 1, fa = fb = 0 and no projector coefficients, so x_0
+            // passes through unchanged
+            double pu = R[r][z + D::IN];
+#pragma unroll
+            for (int ci = 0; ci < NCH; ++ci)
+                if (ci == 0 || ci < nch) pu += L.cs[ch[r][ci].sl()] * ch[r][ci].pv;
+            double x = st.fu * pu - st.fb * b - st.fa * a;
+            if (!cl.valid(r)) x = 0.0;
+            R[r][z + D::IN] = x;
+            bstore(x, rdb, voff[r], sz);  // x_j over x_{j-2}
+            db += x * x;
+            de += x * a;
+            pin(db);
+            pin(de);
+#pragma unroll
+            for (int ci = 0; ci < NCH; ++ci) {
+                if (ci == 0 || ci < nch) {
+                    ch[r][ci].acc += ch[r][ci].pv * x;
+                    pin(ch[r][ci].acc);
+                }
+            }
+            chainsd_advance<UP, C, NCH>(ch[r], snext, L.runs, pvr, z, nch);
+        }
+    };
+#pragma unroll
+    for (int f = 0; f < NO && f < C; ++f) form(f);
+    double vzn[RB];
+    {
+        constexpr int z = D::plane(0, C);
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)z) % (unsigned)n) * 8u);
+    }
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        const int z = D::plane(i, C);
+        if (i + NO < C) form(i + NO);
+        double vz[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            vz[r] = vzn[r];
+            if (i + 1 < C) {
+                const int zn = D::plane(i + 1, C);
+                vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)zn) % (unsigned)n) * 8u);
+            }
+            L.plane[i & 1][cl.pcw[r]] = R[r][z + D::IN];
+        }
+        __syncthreads();
+        const PlaneView<C, double> pv(L.plane[0], i & 1, cl.corner);
+        double yrow[2 * NO + RB];
+        load_yrows_ring<C, D::IN>(pv, R, z, yrow);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const double xz = R[r][z + D::IN];
+            double u = stencil_ring<C, D::IN>(pv, yrow, R[r], r, z, kw) + (vz[r] + kin0) * xz;
+            if (!cl.valid(r)) u = 0.0;
+            R[r][z + D::OUT] = u;
+            da += u * xz;
+            pin(da);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    dots[0] = da;
+    dots[1] = db;
+    dots[2] = de;
+}
+
+template <int C, int NCH>
+__global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_ring_kernel(LaunchArgs K) {
+    using S = Shape<C>;
+    constexpr int RB = S::RB;
+    constexpr int NR = C + NO + 1;
+    static_assert(!S::STREAM, "register ring: resident cubes only");
+    __shared__ Lds<C, double, NCH> L;
+    __shared__ LanczosLds LL;
+    const int tid = threadIdx.x;
+    Cols<C> cl;
+    cl.init(tid);
+    const long long slot_bytes = K.slot_elems * 8;
+    // x_j goes to slot j % 2
+    const __amdgpu_buffer_rsrc_t s0 =
+        make_rsrc(reinterpret_cast<double *>(K.slots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
+    const __amdgpu_buffer_rsrc_t s1 =
+        make_rsrc(reinterpret_cast<double *>(K.wslots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
+    unsigned voff[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * 8u : kIdleOffset;
+    const long long ns = (long long)C * C * C;
+
+    WorkSource work;
+    SnapPtr Ap;
+    long long qfirst, qend, qstep;
+    while (work.next(K, L, tid, Ap, qfirst, qend, qstep)) {
+    const auto &A = *Ap;
+    const int n = A.n;
+    const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
+    const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
+    const int kmax = (long long)A.n_lanczos < ns ? A.n_lanczos : (int)ns;
+    const double rnorm = 1.0 / A.start_norm;
+
+    for (long long q = qfirst; q < qend; q += qstep) {
+        int qi, qj, qk;
+        node_coords(q, n, qi, qj, qk);
+        setup_region(A, L, qi, qj, qk, tid);
+        const int ni = L.ni < kMaxImages ? L.ni : kMaxImages;
+        const int nch = L.nch;
+        const unsigned zbase = (unsigned)pmod(qk - A.m, n);
+        double kw[NO + 1];
+        kw[0] = 0.0;
+#pragma unroll
+        for (int d = 1; d <= NO; ++d) kw[d] = uniform(-0.5 * A.w[d]);
+        const double kin0 = uniform(-3.0 * A.w[0]);
+        unsigned vcol[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            vcol[r] = cl.valid(r) ? (unsigned)(pmod(qi - A.m + cl.x, n) + n * pmod(qj - A.m + cl.y0 + r, n)) * 8u
+                                  : kIdleOffset;
+        // x_0 = v_0[a] = (u(a) - 1/2) / |u - 1/2|, a = local cube index, in the
+        // upward sweep's input layout
+        double R[RB][NR];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const int z = i - (NO + 1);
+                R[r][i] = (z >= 0 && cl.valid(r))
+                              ? (unit_from_seed((unsigned long long)(cl.col[r] + C * C * z)) - 0.5) * rnorm
+                              : 0.0;
+            }
+        for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) L.cs[i] = 0.0;
+        int cur = 0;  // L.s[cur]: dots of x_{j-1}; L.s[cur ^ 1] receives those of x_j
+        double sig_m1 = 1.0, sig_m2 = 0.0;  // sigma_{j-1}, sigma_{j-2}
+        double al_m1 = 0.0, be_m2 = 0.0;    // alpha_{j-1}, beta_{j-2}
+        double gersh = 0.0;
+        int ksteps = kmax;
+        __syncthreads();
+        // one step; returns false when the recurrence ends.  The ring layout
+        // alternates, so steps are taken in (up, down) pairs and every pass of
+        // the loop starts in the upward layout.
+        auto step = [&](int j, auto up) -> bool {
+            constexpr bool UP = decltype(up)::value;
+            LanczosStep st;
+            st.j = j;
+            st.fu = uniform(sig_m1);
+            st.fa = uniform(al_m1 * sig_m1);
+            st.fb = uniform(be_m2 * sig_m2);
+            st.ra = j >= 1;
+            st.rb = j >= 2;
+            const __amdgpu_buffer_rsrc_t rda = (j & 1) ? s0 : s1;  // x_{j-1}
+            const __amdgpu_buffer_rsrc_t rdb = (j & 1) ? s1 : s0;  // x_{j-2}, then x_j
+            double dots[4];
+            lanczos_ring_sweep<C, NCH, UP>(A, L, cl, R, rda, rdb, vr, pvr, vcol, voff, zbase, kw, kin0, st,
+                                           L.s[cur ^ 1], nch, dots);
+            // sum_I c_I s_I(x_j)^2 (the sweep ended on a barrier: every run is closed)
+            double dimg = 0.0;
+            for (int i = fresh_tid(); i < ni; i += S::BLOCK) dimg += L.img_coef[i] * L.s[cur ^ 1][i] * L.s[cur ^ 1][i];
+            dots[3] = dimg;
+            block_sum4(L, dots, tid);
+            double sig = 1.0;
+            if (j >= 1) {
+                const double be = uniform(sqrt(dots[1]));  // beta_{j-1}
+                gersh = fmax(gersh, fabs(al_m1) + be + be_m2);
+                if (tid == 0) {
+                    LL.be[j - 1] = be;
+                    if (!isfinite(be)) atomicOr(A.flags, kFlagLanczos);
+                }
+                if (be <= 1e-13 * gersh) {
+                    ksteps = j;
+                    return false;
+                }
+                sig = uniform(1.0 / be);
+                be_m2 = be;
+            }
+            const double al = j >= 1 ? uniform(sig * sig * (dots[0] + dots[3]) - sig_m1 * dots[2])
+                                     : uniform(dots[0] + dots[3]);
+            if (tid == 0) {
+                LL.al[j] = al;
+                if (!isfinite(al)) atomicOr(A.flags, kFlagLanczos);
+            }
+            if (j == kmax - 1) return false;
+            // coefficients of the next formation: cs = c_I s_I(x_j)
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) {
+                L.cs[i] = i < ni ? L.img_coef[i] * L.s[cur ^ 1][i] : 0.0;
+                L.s[cur][i] = 0.0;
+            }
+            cur ^= 1;
+            sig_m2 = sig_m1;
+            sig_m1 = sig;
+            al_m1 = al;
+            __syncthreads();
+            return true;
+        };
+        for (int j = 0; j < kmax; j += 2) {
+            if (!step(j, std::true_type())) break;
+            if (!step(j + 1, std::false_type())) break;
+        }
+        __syncthreads();
+        if (tid < 64) sturm_extremes(ksteps, LL.al, LL.be, L.bc, tid);
+        __syncthreads();
+        if (tid == 0) {
+            const double lmn = L.bc[0], lmx = L.bc[1];
+            if (A.lmin) A.lmin[q] = lmn;
+            if (A.lmax) A.lmax[q] = lmx;
+            A.chi[q] = 0.5 * (lmx + lmn);
+            A.zeta[q] = (1.0 + A.margin) * 0.5 * (lmx - lmn);
+        }
+        __syncthreads();
+    }
+    }
+}
+
 #if defined(SQ_COMMON_ONLY) || !defined(SQ_CUBES)
 // ---------------------------------------------------------------------------
 // Fermi level, density and energies (Sec. 3.2-3.3).  The Chebyshev sums are
@@ -1590,51 +2249,63 @@ __global__ void sum_partials(const double *partials, int nblk, int width, double
 #define SQ_ALL_CUBES X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29) X(31) X(33) X(35) X(37)
 
 #ifndef SQ_COMMON_ONLY
-// Launch helpers.  Streamed cubes (wider than kResidentCube) are built with
-// two projector chains only; the host rejects deeper sphere overlaps there.
-template <int c>
-hipError_t launch_lanczos_t(const LaunchArgs &a, int nch, int nwg, hipStream_t s) {
+// Launch helpers.  Resident cubes (up to kResidentCube) run the register-ring
+// kernels in FP64 and moments_kernel<c, float> in FP32-mixed mode, built for
+// 1, 2 or 4 projector chains.  Streamed cubes are built with two chains only
+// (the host rejects deeper sphere overlaps there) and run the FP64 streamed
+// kernels in both precisions: with the current vector streamed through
+// memory, FP32 storage saves no registers, and its operand widening made the
+// mixed kernel slower than the FP64 one there.
+template <int c, typename F>
+hipError_t with_chains(int nch, F &&f) {
     if constexpr (!Shape<c>::STREAM) {
-        if (nch > 2) {
-            hipLaunchKernelGGL((lanczos_kernel<c, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
-            return hipGetLastError();
-        }
-    } else if (nch > 2) {
+        if (nch <= 1) return f(std::integral_constant<int, 1>());
+        if (nch <= 2) return f(std::integral_constant<int, 2>());
+        if (nch <= 4) return f(std::integral_constant<int, 4>());
+        return hipErrorInvalidValue;
+    } else {
+        if (nch <= 2) return f(std::integral_constant<int, 2>());
         return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL((lanczos_kernel<c, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
-    return hipGetLastError();
+}
+template <int c>
+hipError_t launch_lanczos_t(const LaunchArgs &a, int nch, int nwg, hipStream_t s) {
+    return with_chains<c>(nch, [&](auto ncht) {
+        constexpr int NCH = decltype(ncht)::value;
+        if constexpr (!Shape<c>::STREAM)
+            hipLaunchKernelGGL((lanczos_ring_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+        else
+            hipLaunchKernelGGL((lanczos_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+        return hipGetLastError();
+    });
 }
 template <int c>
 hipError_t launch_moments_t(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s) {
-    if constexpr (!Shape<c>::STREAM) {
-        if (nch > 2) {
-            if (mixed) hipLaunchKernelGGL((moments_kernel<c, float, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
-            else hipLaunchKernelGGL((moments_kernel<c, double, 4>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
-            return hipGetLastError();
+    return with_chains<c>(nch, [&](auto ncht) {
+        constexpr int NCH = decltype(ncht)::value;
+        if constexpr (!Shape<c>::STREAM) {
+            if (mixed) hipLaunchKernelGGL((moments_kernel<c, float, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            else hipLaunchKernelGGL((moments_ring_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((moments_kernel<c, double, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
         }
-    } else if (nch > 2) {
-        return hipErrorInvalidValue;
-    }
-    if (mixed) hipLaunchKernelGGL((moments_kernel<c, float, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
-    else hipLaunchKernelGGL((moments_kernel<c, double, 2>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
-    return hipGetLastError();
+        return hipGetLastError();
+    });
 }
 template <int c>
 hipError_t occupancy_t(bool lanczos, bool mixed, int nch, int *nb) {
     const int B = Shape<c>::BLOCK;
-    if constexpr (!Shape<c>::STREAM) {
-        if (nch > 2) {
-            if (lanczos) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, 4>, B, 0);
-            if (mixed) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float, 4>, B, 0);
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double, 4>, B, 0);
+    return with_chains<c>(nch, [&](auto ncht) {
+        constexpr int NCH = decltype(ncht)::value;
+        if constexpr (!Shape<c>::STREAM) {
+            if (lanczos) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_ring_kernel<c, NCH>, B, 0);
+            if (mixed) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float, NCH>, B, 0);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_ring_kernel<c, NCH>, B, 0);
+        } else {
+            if (lanczos) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, NCH>, B, 0);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double, NCH>, B, 0);
         }
-    } else if (nch > 2) {
-        return hipErrorInvalidValue;
-    }
-    if (lanczos) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, 2>, B, 0);
-    if (mixed) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float, 2>, B, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double, 2>, B, 0);
+    });
 }
 
 // Per-cube entry points of this translation unit (SQ_CUBES lists its cubes).
