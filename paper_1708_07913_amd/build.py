@@ -29,6 +29,9 @@ DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
                 # the plane loops of the recurrence kernels must unroll fully
                 # (register-resident columns are indexed by plane)
                 "-mllvm", "-pragma-unroll-threshold=1000000"]
+# optional extra -D definitions for the kernels (tuning knobs, e.g.
+# "SQ_MOMENTS_AHEAD=3 SQ_LANCZOS_AHEAD=3")
+DEVICE_FLAGS += ["-D" + d for d in os.environ.get("SQ_DEVICE_DEFINES", "").split()]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__",
               "-I/opt/rocm/include"]
 CXX = os.environ.get("CXX", "g++")

@@ -34,6 +34,22 @@ namespace {
 
 constexpr int NO = kNoMax;
 
+// Prefetch depths (planes) of the vectors the ring kernels read from their
+// workgroup slots: t^{k-1} in the moments sweep, x_{j-1} and x_{j-2} in the
+// Lanczos formation.
+#ifndef SQ_MOMENTS_AHEAD
+#define SQ_MOMENTS_AHEAD 1
+#endif
+#ifndef SQ_LANCZOS_AHEAD
+#define SQ_LANCZOS_AHEAD 1
+#endif
+#ifndef SQ_RING_PPB
+#define SQ_RING_PPB 1
+#endif
+constexpr int kMomentsAhead = SQ_MOMENTS_AHEAD;
+constexpr int kRingPlanesPerBarrier = SQ_RING_PPB;  // 1 or 2 (four plane buffers)
+constexpr int kLanczosAhead = SQ_LANCZOS_AHEAD;
+
 // Rows of the cube owned by one thread: one column up to 27 points (a
 // workgroup of C^2 threads, 7-12 waves for 21-27 points), two y-adjacent
 // columns for 29 and 31 points (512-thread workgroups, 256 VGPRs per lane; the
@@ -1529,69 +1545,94 @@ __device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, N
     for (int r = 0; r < RB; ++r) chainsd_start<UP>(L, pvr, Cols<C>::column(r), ch[r], nch);
     unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
     asm volatile("" : "+s"(zb));
-    double vzn[RB], tpn[RB];
-    {
-        constexpr int z = D::plane(0, C);
+    // PPB planes share one barrier (their LDS planes are written together);
+    // V_eff runs PPB planes ahead and t^{k-1} TPA planes ahead.  At k = 0 the
+    // t^{k-1} loads use the idle offset (they read 0) instead of a branch,
+    // which would serialise the prefetch.
+    constexpr int PPB = kRingPlanesPerBarrier;
+    constexpr int TPA = kMomentsAhead > PPB ? kMomentsAhead : PPB;
+    unsigned poff[RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)z) % (unsigned)n) * 8u);
-            tpn[r] = st.prev ? bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u) : 0.0;
-        }
+    for (int r = 0; r < RB; ++r) poff[r] = st.prev ? voff[r] : kIdleOffset;
+    double vzq[PPB][RB], tpn[TPA][RB];
+    auto vload = [&](int i, int r) {
+        const int zz = D::plane(i, C);
+        return bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)zz) % (unsigned)n) * 8u);
+    };
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+#pragma unroll
+        for (int a = 0; a < PPB; ++a) vzq[a][r] = a < C ? vload(a, r) : 0.0;
+#pragma unroll
+        for (int a = 0; a < TPA; ++a)
+            tpn[a][r] = a < C ? bload<double>(slr, poff[r], (unsigned)(D::plane(a, C) * S::CC) * 8u) : 0.0;
     }
 #pragma unroll
-    for (int i = 0; i < C; ++i) {
-        const int z = D::plane(i, C);
-        const unsigned sz = (unsigned)(z * S::CC) * 8u;
-        double vz[RB], tprev[RB];
+    for (int g = 0; g < C; g += PPB) {
+        const int pb = PPB * ((g / PPB) & 1);
+        double vz[PPB][RB], tprev[PPB][RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            vz[r] = vzn[r];
-            tprev[r] = tpn[r];
-            if (i + 1 < C) {
-                const int zn = D::plane(i + 1, C);
-                vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)zn) % (unsigned)n) * 8u);
-                if (st.prev) tpn[r] = bload<double>(slr, voff[r], (unsigned)(zn * S::CC) * 8u);
+        for (int h = 0; h < PPB; ++h) {
+            const int i = g + h;
+            if (i < C) {
+                const int z = D::plane(i, C);
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    vz[h][r] = vzq[i % PPB][r];
+                    tprev[h][r] = tpn[i % TPA][r];
+                    if (i + PPB < C) vzq[i % PPB][r] = vload(i + PPB, r);
+                    if (i + TPA < C)
+                        tpn[i % TPA][r] = bload<double>(slr, poff[r], (unsigned)(D::plane(i + TPA, C) * S::CC) * 8u);
+                    L.plane[pb + h][cl.pcw[r]] = R[r][z + D::IN];
+                }
             }
-            L.plane[i & 1][cl.pcw[r]] = R[r][z + D::IN];
         }
         __syncthreads();
-        const PlaneView<C, double> pv(L.plane[0], i & 1, cl.corner);
-        double yrow[2 * NO + RB];
-        load_yrows_ring<C, D::IN>(pv, R, z, yrow);
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const double acc = stencil_ring<C, D::IN>(pv, yrow, R[r], r, z, kw);
-            const double tz = R[r][z + D::IN];
-            const double u = acc + (vz[r] + st.c0) * st.invz * tz;
-            double pval[NCH];
-            double nvd = st.al * u - tprev[r];
+        for (int h = 0; h < PPB; ++h) {
+            const int i = g + h;
+            if (i < C) {
+                const int z = D::plane(i, C);
+                const unsigned sz = (unsigned)(z * S::CC) * 8u;
+                const PlaneView<C, double> pv(L.plane[0], pb + h, cl.corner);
+                double yrow[2 * NO + RB];
+                load_yrows_ring<C, D::IN>(pv, R, z, yrow);
 #pragma unroll
-            for (int ci = 0; ci < NCH; ++ci) {
-                pval[ci] = 0.0;
-                if (ci == 0 || ci < nch) {
-                    pval[ci] = ch[r][ci].pv;
-                    nvd += L.cs[ch[r][ci].sl()] * pval[ci];
+                for (int r = 0; r < RB; ++r) {
+                    const double acc = stencil_ring<C, D::IN>(pv, yrow, R[r], r, z, kw);
+                    const double tz = R[r][z + D::IN];
+                    const double u = acc + (vz[h][r] + st.c0) * st.invz * tz;
+                    double pval[NCH];
+                    double nvd = st.al * u - tprev[h][r];
+#pragma unroll
+                    for (int ci = 0; ci < NCH; ++ci) {
+                        pval[ci] = 0.0;
+                        if (ci == 0 || ci < nch) {
+                            pval[ci] = ch[r][ci].pv;
+                            nvd += L.cs[ch[r][ci].sl()] * pval[ci];
+                        }
+                    }
+                    if (!cl.valid(r)) nvd = 0.0;
+                    R[r][z + D::OUT] = nvd;
+                    bstore(tz, slr, voff[r], sz);  // t^k over t^{k-1}
+                    d1 += nvd * nvd;
+                    d2 += nvd * tz;
+                    pin(d1);
+                    pin(d2);
+#pragma unroll
+                    for (int ci = 0; ci < NCH; ++ci) {
+                        if (ci == 0 || ci < nch) {
+                            ch[r][ci].acc += pval[ci] * nvd;
+                            pin(ch[r][ci].acc);
+                        }
+                    }
+                    chainsd_advance<UP, C, NCH>(ch[r], snext, L.runs, pvr, z, nch);
+                    if (z == MC && centre_r == r) {
+                        mrow[st.k + 1] = nvd;
+                        if (st.k == 0) L.bc[2] = nvd;
+                        if (fabs(nvd) > 1.0 + A.bounds_tol) atomicOr(A.flags, kFlagBounds);
+                    }
                 }
-            }
-            if (!cl.valid(r)) nvd = 0.0;
-            R[r][z + D::OUT] = nvd;
-            bstore(tz, slr, voff[r], sz);  // t^k over t^{k-1}
-            d1 += nvd * nvd;
-            d2 += nvd * tz;
-            pin(d1);
-            pin(d2);
-#pragma unroll
-            for (int ci = 0; ci < NCH; ++ci) {
-                if (ci == 0 || ci < nch) {
-                    ch[r][ci].acc += pval[ci] * nvd;
-                    pin(ch[r][ci].acc);
-                }
-            }
-            chainsd_advance<UP, C, NCH>(ch[r], snext, L.runs, pvr, z, nch);
-            if (z == MC && centre_r == r) {
-                mrow[st.k + 1] = nvd;
-                if (st.k == 0) L.bc[2] = nvd;
-                if (fabs(nvd) > 1.0 + A.bounds_tol) atomicOr(A.flags, kFlagBounds);
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -1741,7 +1782,7 @@ __device__ __forceinline__ void lanczos_ring_sweep(const AT &A, Lds<C, double, N
     using S = Shape<C>;
     using D = RingDir<UP>;
     constexpr int RB = S::RB;
-    constexpr int FA = 1;  // slot reads run FA planes ahead of the formation
+    constexpr int FA = kLanczosAhead;  // slot reads run FA planes ahead of the formation
     const int n = A.n;
     ChainD<UP> ch[RB][NCH];
 #pragma unroll
@@ -1807,39 +1848,54 @@ __device__ __forceinline__ void lanczos_ring_sweep(const AT &A, Lds<C, double, N
     };
 #pragma unroll
     for (int f = 0; f < NO && f < C; ++f) form(f);
-    double vzn[RB];
-    {
-        constexpr int z = D::plane(0, C);
+    // PPB planes share one barrier; V_eff runs PPB planes ahead
+    constexpr int PPB = kRingPlanesPerBarrier;
+    double vzq[PPB][RB];
+    auto vload = [&](int i, int r) {
+        const int zz = D::plane(i, C);
+        return bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)zz) % (unsigned)n) * 8u);
+    };
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
-            vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)z) % (unsigned)n) * 8u);
-    }
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-    for (int i = 0; i < C; ++i) {
-        const int z = D::plane(i, C);
-        if (i + NO < C) form(i + NO);
-        double vz[RB];
+        for (int a = 0; a < PPB; ++a) vzq[a][r] = a < C ? vload(a, r) : 0.0;
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            vz[r] = vzn[r];
-            if (i + 1 < C) {
-                const int zn = D::plane(i + 1, C);
-                vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)zn) % (unsigned)n) * 8u);
+    for (int g = 0; g < C; g += PPB) {
+        const int pb = PPB * ((g / PPB) & 1);
+        double vz[PPB][RB];
+#pragma unroll
+        for (int h = 0; h < PPB; ++h) {
+            const int i = g + h;
+            if (i < C) {
+                const int z = D::plane(i, C);
+                if (i + NO < C) form(i + NO);
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    vz[h][r] = vzq[i % PPB][r];
+                    if (i + PPB < C) vzq[i % PPB][r] = vload(i + PPB, r);
+                    L.plane[pb + h][cl.pcw[r]] = R[r][z + D::IN];
+                }
             }
-            L.plane[i & 1][cl.pcw[r]] = R[r][z + D::IN];
         }
         __syncthreads();
-        const PlaneView<C, double> pv(L.plane[0], i & 1, cl.corner);
-        double yrow[2 * NO + RB];
-        load_yrows_ring<C, D::IN>(pv, R, z, yrow);
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const double xz = R[r][z + D::IN];
-            double u = stencil_ring<C, D::IN>(pv, yrow, R[r], r, z, kw) + (vz[r] + kin0) * xz;
-            if (!cl.valid(r)) u = 0.0;
-            R[r][z + D::OUT] = u;
-            da += u * xz;
-            pin(da);
+        for (int h = 0; h < PPB; ++h) {
+            const int i = g + h;
+            if (i < C) {
+                const int z = D::plane(i, C);
+                const PlaneView<C, double> pv(L.plane[0], pb + h, cl.corner);
+                double yrow[2 * NO + RB];
+                load_yrows_ring<C, D::IN>(pv, R, z, yrow);
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const double xz = R[r][z + D::IN];
+                    double u = stencil_ring<C, D::IN>(pv, yrow, R[r], r, z, kw) + (vz[h][r] + kin0) * xz;
+                    if (!cl.valid(r)) u = 0.0;
+                    R[r][z + D::OUT] = u;
+                    da += u * xz;
+                    pin(da);
+                }
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
     }
