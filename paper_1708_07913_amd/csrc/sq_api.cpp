@@ -69,6 +69,10 @@ struct sq_ctx {
     char *ws = nullptr;
     const double *veff = nullptr;
     int state = kSetup;
+    // bumped whenever chi/zeta are rewritten (sq_spectral_bounds, sq_set_bounds,
+    // a batched pass with bounds), so a batch can tell whether the bounds it
+    // would reuse are still its own
+    unsigned long long bounds_gen = 0;
 
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -375,6 +379,7 @@ struct sq_batch {
     long long passes = 0;
     bool have_bounds = false;
     std::vector<double> slack;       // per snapshot: min_q zeta_q margin / (1 + margin) of the last bounds
+    std::vector<unsigned long long> gen_seen;  // per snapshot: bounds generation after the last batched pass
     size_t off_vref = 0, off_red = 0;  // V_eff at the last bounds; reduction outputs (2 per snapshot)
 
     template <typename T>
@@ -919,6 +924,7 @@ int sq_spectral_bounds(sq_ctx *c, double *lmin, double *lmax, void *stream) {
         if (rc) return rc;
         rc = hip_check(sq::launch_lanczos(k, c->C, c->nch, c->nwg_lanczos, s), "launching Lanczos");
         if (rc) return rc;
+        ++c->bounds_gen;
         rc = read_flags(c, s);
         if (rc) return rc;
         c->state = kBounds;
@@ -934,6 +940,7 @@ int sq_set_bounds(sq_ctx *c, const double *lmin, const double *lmax, void *strea
                                          c->opt.margin, static_cast<hipStream_t>(stream)),
                    "set bounds");
     if (rc) return rc;
+    ++c->bounds_gen;
     c->state = kBounds;
     return SQ_OK;
 }
@@ -1182,6 +1189,10 @@ int sq_batch_step(sq_batch *b, double *mu, double *energies, void *stream) {
         // bounds on the first pass, every bounds_every passes, and whenever
         // V_eff has moved too far for the previous ones
         bool bounds = !b->have_bounds || b->opt.bounds_every <= 1 || b->passes % b->opt.bounds_every == 0;
+        // bounds rewritten outside the batch since its last pass are not the
+        // ones whose margin slack the batch recorded
+        for (size_t i = 0; !bounds && i < b->ctx.size(); ++i)
+            if (b->ctx[i]->bounds_gen != b->gen_seen[i]) bounds = true;
         if (!bounds) {
             bool safe = false;
             rc = reuse_is_safe(b, b->own, &safe);
@@ -1225,6 +1236,11 @@ int sq_batch_step(sq_batch *b, double *mu, double *energies, void *stream) {
         if (!rc) {
             ++b->passes;
             b->have_bounds = true;
+            b->gen_seen.resize(b->ctx.size());
+            for (size_t i = 0; i < b->ctx.size(); ++i) {
+                if (bounds) ++b->ctx[i]->bounds_gen;
+                b->gen_seen[i] = b->ctx[i]->bounds_gen;
+            }
         }
         const int rc2 = hip_check(hipEventRecord(b->ev_out, b->own), "ordering the batch");
         if (!rc2) (void)hipStreamWaitEvent(caller, b->ev_out, 0);
@@ -1240,6 +1256,7 @@ int sq_batch_autotune(sq_batch *b, const char *cache_path, void *stream) {
         int rc = hip_check(hipStreamSynchronize(caller), "autotune");
         if (rc) return rc;
         drop_graph(b);
+        b->have_bounds = false;  // the tuning runs rewrite chi and zeta
         const std::string key = tune_key(b);
         int best_block = 0, best_wg = 0;
         if (!cache_lookup(cache_path, key, &best_block, &best_wg)) {

@@ -173,33 +173,49 @@ def test_batch_ensemble_sampled():
 
 
 def test_batch_bounds_reuse_across_veff_update():
-    """bounds_every = 3: passes 2 and 3 reuse the first pass's bounds after a small
-    V_eff change; the result matches a fresh single-snapshot pass on those same
-    bounds, and a pass whose reused bounds are too tight is redone."""
+    """bounds_every = 1000: pass 2 reuses the first pass's bounds after a small
+    V_eff change and matches a fresh single-snapshot pass on those same bounds.
+    Bounds rewritten outside the batch (sq_set_bounds) are not reused: the next
+    pass computes fresh ones.  After a large V_eff change (beyond the margin
+    slack) the pass also computes fresh bounds."""
     sq = _sq()
     wls = _small_ensemble()[:2]
     print("case bounds reuse", flush=True)
     snaps = _snaps(wls)
-    b = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=True, bounds_every=3)
+    refs = _snaps(wls)  # separate contexts for the reference passes
+    b = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=True, bounds_every=1000)
     b.step()
-    lo_hi = [g.spectral_bounds() for g in snaps]  # the bounds the batch just used
-    for g, wl in zip(snaps, wls):
-        g.update_veff(torch.from_numpy(0.98 * wl.veff()).cuda())
+    lo_hi = [g.spectral_bounds() for g in refs]  # the bounds the batch just computed
+
+    def set_veff(scale):
+        for g, r, wl in zip(snaps, refs, wls):
+            v = torch.from_numpy(scale * wl.veff()).cuda()
+            g.update_veff(v)
+            r.update_veff(v)
+
+    def check_fresh(mu, e):
+        for i, (r, wl) in enumerate(zip(refs, wls)):
+            mom1, mu1, rho1, e1 = r.scf_pass(wl.n_electrons)
+            assert abs(mu[i] - mu1) < 1e-11, (mu[i], mu1)
+            assert np.abs(_np(b.rho[i]) - _np(rho1)).max() < 1e-12 * _np(rho1).max()
+
+    set_veff(0.98)
     mu, e = b.step()  # reuses the first pass's bounds
-    for i, (g, wl) in enumerate(zip(snaps, wls)):
-        g.set_bounds(*lo_hi[i])
-        mom = g.moments()
-        mu1 = g.fermi_level(mom, wl.n_electrons)
-        rho1, e1 = g.density_energy(mom, mu1)
+    for i, (r, wl) in enumerate(zip(refs, wls)):
+        r.set_bounds(*lo_hi[i])
+        mom = r.moments()
+        mu1 = r.fermi_level(mom, wl.n_electrons)
+        rho1, e1 = r.density_energy(mom, mu1)
         assert abs(mu[i] - mu1) < 1e-11
-        r = _np(b.rho[i])
-        assert np.abs(r - _np(rho1)).max() < 1e-12 * _np(rho1).max()
-        assert abs(e[i][3] - wl.n_electrons) < 1e-10 * wl.n_electrons
-    # a large change: the reused bounds no longer hold, the pass is redone
-    for g, wl in zip(snaps, wls):
-        g.update_veff(torch.from_numpy(3.0 * wl.veff()).cuda())
-    mu, e = b.step()
-    for i, (g, wl) in enumerate(zip(snaps, wls)):
-        mom1, mu1, rho1, e1 = g.scf_pass(wl.n_electrons)
-        assert abs(mu[i] - mu1) < 1e-11, (mu[i], mu1)
         assert np.abs(_np(b.rho[i]) - _np(rho1)).max() < 1e-12 * _np(rho1).max()
+        assert abs(e[i][3] - wl.n_electrons) < 1e-10 * wl.n_electrons
+    # bounds injected from outside (here far too tight): not reused
+    lo, hi = lo_hi[0]
+    mid = 0.5 * (lo + hi)
+    snaps[0].set_bounds(mid - 0.1, mid + 0.1)
+    mu, e = b.step()
+    check_fresh(mu, e)
+    # a large change: beyond the margin slack, the previous bounds no longer hold
+    set_veff(3.0)
+    mu, e = b.step()
+    check_fresh(mu, e)

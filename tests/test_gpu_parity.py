@@ -4,7 +4,7 @@ Tolerances (FP64 path): moments |d rho^j| <= 1e-10 (moments are bounded by 1),
 density max|d rho| / max rho <= 1e-10, energies 1e-10 relative.  Moment parity
 is checked on bounds injected from the other side, because Ritz values of two
 independent FP64 Lanczos runs agree only to rounding amplified by the
-recurrence (bounds themselves: 1e-8 relative).  Mixed precision: density
+recurrence (bounds themselves: 1e-12 relative).  Mixed precision: density
 1e-5 relative and energies 1e-6 Ha/atom against the FP64 oracle.
 """
 from __future__ import annotations
@@ -17,6 +17,10 @@ from paper_1708_07913_amd import workloads as W
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+# Lanczos bounds of two FP64 implementations (GPU: the one-pass recurrence,
+# oracle: Paige's ordering) agree to rounding; observed <= 1e-15 relative
+BOUNDS_RTOL = 1e-12
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -58,8 +62,10 @@ def test_tiny_cell_fp64_pipeline():
     # bounds
     glo, ghi = g.spectral_bounds()
     scale = np.abs(lmax).max()
-    assert np.abs(_np(glo) - lmin).max() < 1e-8 * scale
-    assert np.abs(_np(ghi) - lmax).max() < 1e-8 * scale
+    print(f"bounds rel {np.abs(_np(glo) - lmin).max() / scale:.2e} {np.abs(_np(ghi) - lmax).max() / scale:.2e}",
+          flush=True)
+    assert np.abs(_np(glo) - lmin).max() < BOUNDS_RTOL * scale
+    assert np.abs(_np(ghi) - lmax).max() < BOUNDS_RTOL * scale
     # moments on the oracle's bounds
     g.set_bounds(torch.from_numpy(lmin), torch.from_numpy(lmax))
     mom = g.moments()
@@ -107,8 +113,10 @@ def test_edge_cases_moments_and_bounds(name):
     lmin, lmax = ref.bounds()
     glo, ghi = g.spectral_bounds()
     scale = np.abs(lmax).max()
-    assert np.abs(_np(glo) - lmin).max() < 1e-8 * scale
-    assert np.abs(_np(ghi) - lmax).max() < 1e-8 * scale
+    print(f"bounds rel {np.abs(_np(glo) - lmin).max() / scale:.2e} {np.abs(_np(ghi) - lmax).max() / scale:.2e}",
+          flush=True)
+    assert np.abs(_np(glo) - lmin).max() < BOUNDS_RTOL * scale
+    assert np.abs(_np(ghi) - lmax).max() < BOUNDS_RTOL * scale
     g.set_bounds(torch.from_numpy(lmin), torch.from_numpy(lmax))
     m = _np(g.moments())
     mom_ref = ref.moments(lmin, lmax)
@@ -140,8 +148,11 @@ def test_mixed_precision_tiny_cell():
     assert err2 < 1e-5, err2
 
 
-@pytest.mark.parametrize("kT,npl", [(0.5, 32), (5.0, 32), (0.5, 96), (5.0, 96)])
-def test_mixed_precision_sweep_corners(kT, npl):
+@pytest.mark.parametrize("kT", [0.5, 1.0, 2.0, 5.0])
+@pytest.mark.parametrize("npl", [32, 48, 96])
+def test_mixed_precision_sweep(kT, npl):
+    """The mixed-precision sweep of the tiny cell: every (kT, n_pl) point
+    against the FP64 oracle at the oracle's bounds and Fermi level."""
     sq = _sq()
     wl = W.tiny_cell(precision="mixed", npl=npl, kT_eV=kT)
     print(f"case mixed kT={kT} npl={npl}", flush=True)
@@ -151,10 +162,18 @@ def test_mixed_precision_sweep_corners(kT, npl):
     mu_ref, _ = ref.fermi_level(lmin, lmax, mom_ref, wl.n_electrons)
     rho_ref, e_ref = ref.density_energy(lmin, lmax, mom_ref, mu_ref)
     g.set_bounds(torch.from_numpy(lmin), torch.from_numpy(lmax))
-    rho, e = g.density_energy(g.moments(), mu_ref)
+    mom = g.moments()
+    rho, e = g.density_energy(mom, mu_ref)
     err = np.abs(_np(rho) - rho_ref).max() / rho_ref.max()
+    print(f"mixed kT={kT} npl={npl}: rho {err:.2e}  dE_band/atom {abs(e[0] - e_ref[0]) / wl.natom:.2e}  "
+          f"dF/atom {abs(e[2] - e_ref[2]) / wl.natom:.2e}  dN {abs(e[3] - e_ref[3]):.2e}", flush=True)
     assert err < 1e-5, err
+    assert abs(e[0] - e_ref[0]) / wl.natom < 1e-6
     assert abs(e[2] - e_ref[2]) / wl.natom < 1e-6
+    # the electron count at the mixed path's own Fermi level
+    mu = g.fermi_level(mom, wl.n_electrons)
+    _, e2 = g.density_energy(mom, mu)
+    assert abs(e2[3] - wl.n_electrons) < 1e-9 * wl.n_electrons
 
 
 def _sampled_parity(wl, nsample, seed=0):
@@ -171,8 +190,10 @@ def _sampled_parity(wl, nsample, seed=0):
     # bounds of the sampled nodes
     olo, ohi = ref.bounds(nodes)
     scale = np.abs(ohi).max()
-    assert np.abs(glo[nodes] - olo).max() < 1e-8 * scale
-    assert np.abs(ghi[nodes] - ohi).max() < 1e-8 * scale
+    print(f"bounds rel {np.abs(glo[nodes] - olo).max() / scale:.2e} {np.abs(ghi[nodes] - ohi).max() / scale:.2e}",
+          flush=True)
+    assert np.abs(glo[nodes] - olo).max() < BOUNDS_RTOL * scale
+    assert np.abs(ghi[nodes] - ohi).max() < BOUNDS_RTOL * scale
     # moments of the sampled nodes on the GPU's bounds
     mom_ref = ref.moments(glo[nodes], ghi[nodes], nodes=nodes)
     assert np.abs(m[nodes] - mom_ref).max() < 1e-10
