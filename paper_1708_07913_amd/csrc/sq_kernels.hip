@@ -47,6 +47,8 @@ constexpr int NO = kNoMax;
 #define SQ_RING_PPB 1
 #endif
 constexpr int kMomentsAhead = SQ_MOMENTS_AHEAD;
+// FP32-mixed moments: leading steps run in FP64 (see moments_mixed_kernel)
+constexpr int kMixedFp64Steps = 4;
 constexpr int kRingPlanesPerBarrier = SQ_RING_PPB;  // 1 or 2 (four plane buffers)
 constexpr int kLanczosAhead = SQ_LANCZOS_AHEAD;
 
@@ -935,6 +937,10 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
                     // a real column; it must stay zero, since it is that column's
                     // y neighbour
                     if (!cl.valid(r)) nvd = 0.0;
+                    // the moment t^{k+1}[q] is taken before the vector is
+                    // stored: with FP32 storage its rounding would otherwise
+                    // enter rho^{k+1} directly (and alike for every node)
+                    const double moment = nvd;
                     const T nvt = T(nvd);
                     nvd = (double)nvt;
                     if (kResident) {
@@ -958,9 +964,9 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
                     }
                     chains_advance<C, NCH>(ch[r], snext, L.runs, pvr, z, nch);
                     if (z == MC && centre_r == r) {
-                        mrow[k + 1] = nvd;
-                        if (k == 0) L.bc[2] = nvd;
-                        if (fabs(nvd) > 1.0 + A.bounds_tol) atomicOr(A.flags, kFlagBounds);
+                        mrow[k + 1] = moment;
+                        if (k == 0) L.bc[2] = moment;
+                        if (fabs(moment) > 1.0 + A.bounds_tol) atomicOr(A.flags, kFlagBounds);
                     }
                 }
             }
@@ -1747,6 +1753,252 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_ring_kernel(LaunchArg
 }
 
 // ---------------------------------------------------------------------------
+// FP32-mixed Chebyshev moments (resident cubes).  The first kMixedFp64Steps
+// steps run on the FP64 register ring (moments_ring_sweep): the early vectors
+// are concentrated around q with entries of order one, and an FP32 rounding
+// of them propagates into every later moment, alike for every node.  The
+// remaining steps keep t^k and t^{k-1} in FP32 registers (t^{k+1} overwrites
+// t^{k-1} in place; no vector moves through memory).  Every operand is
+// widened before it is used and all arithmetic is FP64; the LDS plane holds
+// the widened t^k, so its x and y legs need no conversion.
+// ---------------------------------------------------------------------------
+template <int C, int NCH, typename AT>
+__device__ __forceinline__ void mixed_sweep(const AT &A, Lds<C, double, NCH> &L, const Cols<C> &cl,
+                                            float (&tv)[Shape<C>::RB][C], float (&tp)[Shape<C>::RB][C],
+                                            __amdgpu_buffer_rsrc_t vr, __amdgpu_buffer_rsrc_t pvr,
+                                            const unsigned (&vcol)[Shape<C>::RB], unsigned zbase,
+                                            const double (&kw)[NO + 1], const MomentsStep &st, double *snext,
+                                            int nch, int centre_r, double *mrow, double &d1, double &d2) {
+    using S = Shape<C>;
+    constexpr int RB = S::RB;
+    constexpr int MC = (C - 1) / 2;
+    constexpr int P = S::P;
+    // The LDS plane holds the widened t^k (FP64): an FP32 plane halves the
+    // LDS bytes but its x and y legs then need a conversion at every use,
+    // which measured 10 % slower on the 1372-atom cell.
+    using PT = double;
+    double *plane = &L.plane[0][0];
+    const int n = A.n;
+    ChainD<true> ch[RB][NCH];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) chainsd_start<true>(L, pvr, Cols<C>::column(r), ch[r], nch);
+    unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
+    asm volatile("" : "+s"(zb));
+    double vzn[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) vzn[r] = bload<double>(vr, vcol[r], (unsigned)(n * n) * (zb % (unsigned)n) * 8u);
+#pragma unroll
+    for (int z = 0; z < C; ++z) {
+        double vz[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            vz[r] = vzn[r];
+            if (z + 1 < C)
+                vzn[r] = bload<double>(vr, vcol[r],
+                                       (unsigned)(n * n) * ((zb + (unsigned)(z + 1)) % (unsigned)n) * 8u);
+            plane[(z & 1) * S::PLANE + cl.pcw[r]] = (PT)tv[r][z];
+        }
+        __syncthreads();
+        const PlaneView<C, PT> pv(plane, z & 1, cl.corner);
+        PT yrow[2 * NO + RB];
+#pragma unroll
+        for (int j = 0; j < NO; ++j) yrow[j] = pv.ylo[j * P];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) yrow[NO + r] = (PT)tv[r][z];
+#pragma unroll
+        for (int j = 0; j < NO; ++j) yrow[NO + RB + j] = pv.yhi[j * P];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            double acc[2] = {0.0, 0.0};
+#pragma unroll
+            for (int d = 1; d <= NO; ++d) {
+                const double xs = (double)pv.xr[r * P + NO + d] + (double)pv.xr[r * P + NO - d];
+                const double ys = widen_at_use(yrow[NO + r + d]) + widen_at_use(yrow[NO + r - d]);
+                double zs = 0.0;
+                if (z + d < C) zs = widen_at_use(tv[r][z + d]);
+                if (z - d >= 0) zs = zs + widen_at_use(tv[r][z - d]);
+                acc[d & 1] += kw[d] * (xs + ys + zs);
+            }
+            const double tz = widen_at_use(tv[r][z]);
+            const double u = acc[1] + acc[0] + (vz[r] + st.c0) * st.invz * tz;
+            double pval[NCH];
+            double nvd = st.al * u - widen_at_use(tp[r][z]);
+#pragma unroll
+            for (int ci = 0; ci < NCH; ++ci) {
+                pval[ci] = 0.0;
+                if (ci == 0 || ci < nch) {
+                    pval[ci] = ch[r][ci].pv;
+                    nvd += L.cs[ch[r][ci].sl()] * pval[ci];
+                }
+            }
+            if (!cl.valid(r)) nvd = 0.0;
+            // the moment is taken before the vector is rounded for storage
+            const double moment = nvd;
+            tp[r][z] = (float)nvd;  // t^{k+1} over t^{k-1}
+            nvd = (double)tp[r][z];
+            d1 += nvd * nvd;
+            d2 += nvd * tz;
+            pin(d1);
+            pin(d2);
+#pragma unroll
+            for (int ci = 0; ci < NCH; ++ci) {
+                if (ci == 0 || ci < nch) {
+                    ch[r][ci].acc += pval[ci] * nvd;
+                    pin(ch[r][ci].acc);
+                }
+            }
+            chainsd_advance<true, C, NCH>(ch[r], snext, L.runs, pvr, z, nch);
+            if (z == MC && centre_r == r) {
+                mrow[st.k + 1] = moment;
+                if (fabs(moment) > 1.0 + A.bounds_tol) atomicOr(A.flags, kFlagBounds);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int C, int NCH>
+__global__ __launch_bounds__(Shape<C>::BLOCK) void moments_mixed_kernel(LaunchArgs K) {
+    using S = Shape<C>;
+    constexpr int RB = S::RB;
+    constexpr int MC = (C - 1) / 2;
+    constexpr int NR = C + NO + 1;
+    static_assert(!S::STREAM, "resident cubes only");
+    __shared__ Lds<C, double, NCH> L;
+    const int tid = threadIdx.x;
+    Cols<C> cl;
+    cl.init(tid);
+    int centre_r = -1;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (cl.col[r] == MC * C + MC) centre_r = r;
+    const long long slot_bytes = K.slot_elems * 8;
+    const __amdgpu_buffer_rsrc_t slr =
+        make_rsrc(reinterpret_cast<double *>(K.slots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
+    unsigned voff[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * 8u : kIdleOffset;
+
+    WorkSource work;
+    SnapPtr Ap;
+    long long qfirst, qend, qstep;
+    while (work.next(K, L, tid, Ap, qfirst, qend, qstep)) {
+    const auto &A = *Ap;
+    const int n = A.n;
+    const int npl = A.npl, half = npl / 2;
+    // FP64 steps: an even number (the ring sweeps come in up/down pairs)
+    const int k64 = (kMixedFp64Steps < half ? kMixedFp64Steps : half) & ~1;
+    const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
+    const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
+    const double kin0 = -3.0 * A.w[0];
+
+    for (long long q = qfirst; q < qend; q += qstep) {
+        int qi, qj, qk;
+        node_coords(q, n, qi, qj, qk);
+        setup_region(A, L, qi, qj, qk, tid);
+        const int ni = L.ni < kMaxImages ? L.ni : kMaxImages;
+        const int nch = L.nch;
+        const unsigned zbase = (unsigned)pmod(qk - A.m, n);
+        const double chi = uniform(A.chi[q]), zeta = uniform(A.zeta[q]);
+        const double invz = uniform(1.0 / zeta);
+        double kw[NO + 1];
+        kw[0] = 0.0;
+#pragma unroll
+        for (int d = 1; d <= NO; ++d) kw[d] = uniform(-0.5 * A.w[d] * invz);
+        unsigned vcol[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            vcol[r] = cl.valid(r) ? (unsigned)(pmod(qi - A.m + cl.x, n) + n * pmod(qj - A.m + cl.y0 + r, n)) * 8u
+                                  : kIdleOffset;
+        double *mrow = A.moments + q * (long long)(npl + 1);
+        if (tid == 0) mrow[0] = 1.0;
+        int cur = 0;
+        projector_dots<false>(L, pvr, cl, cur, nch, [&](int r, int z) {
+            return (centre_r == r && z == MC) ? 1.0 : 0.0;
+        });
+        MomentsStep st;
+        st.invz = invz;
+        st.c0 = uniform(kin0 - chi);
+        auto begin_step = [&](int k) {
+            st.al = k == 0 ? 1.0 : 2.0;
+            st.k = k;
+            st.prev = k > 0;
+            const double scale = uniform(st.al * invz);
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK)
+                L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur][i] : 0.0;
+            __syncthreads();
+        };
+        auto end_step = [&](int k, double d1, double d2) {
+            block_sum2(L, d1, d2, tid);
+            if (k + 1 > half / 2) {
+                if (tid == 0) {
+                    const double r2k = 2.0 * d1 - 1.0, r2k1 = 2.0 * d2 - mrow[1];
+                    mrow[2 * (k + 1)] = r2k;
+                    mrow[2 * (k + 1) - 1] = r2k1;
+                    if (fabs(r2k) > 1.0 + A.bounds_tol || fabs(r2k1) > 1.0 + A.bounds_tol)
+                        atomicOr(A.flags, kFlagBounds);
+                }
+            }
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) L.s[cur][i] = 0.0;
+            cur ^= 1;
+            __syncthreads();
+        };
+        // FP64 phase on the ring; t^{k-1} in the slot
+        {
+            double R[RB][NR];
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    const int z = i - (NO + 1);
+                    R[r][i] = (z >= 0 && centre_r == r && z == MC) ? 1.0 : 0.0;
+                }
+            for (int k = 0; k < k64; k += 2) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    begin_step(k + h);
+                    double d1 = 0.0, d2 = 0.0;
+                    if (h == 0)
+                        moments_ring_sweep<C, NCH, true>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st,
+                                                         L.s[cur ^ 1], nch, centre_r, mrow, d1, d2);
+                    else
+                        moments_ring_sweep<C, NCH, false>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st,
+                                                          L.s[cur ^ 1], nch, centre_r, mrow, d1, d2);
+                    end_step(k + h, d1, d2);
+                }
+            }
+            // FP32 phase: t^k from the ring (upward input layout after an even
+            // number of steps), t^{k-1} from the slot, both rounded once
+            float tv[RB][C], tp[RB][C];
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int z = 0; z < C; ++z) {
+                    tv[r][z] = (float)R[r][z + NO + 1];
+                    tp[r][z] = k64 > 0 ? (float)bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u) : 0.0f;
+                }
+            for (int k = k64; k < half; ++k) {
+                begin_step(k);
+                double d1 = 0.0, d2 = 0.0;
+                mixed_sweep<C, NCH>(A, L, cl, tv, tp, vr, pvr, vcol, zbase, kw, st, L.s[cur ^ 1], nch, centre_r,
+                                    mrow, d1, d2);
+                end_step(k, d1, d2);
+                // t^k -> t^{k-1}, t^{k+1} -> t^k
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int z = 0; z < C; ++z) {
+                        const float t = tv[r][z];
+                        tv[r][z] = tp[r][z];
+                        tp[r][z] = t;
+                    }
+            }
+        }
+    }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Lanczos bounds on the register ring, one pass per step (Sec. 3.2; Paige's
 // ordering up to rounding).  x_j denotes w_{j-1} = beta_{j-1} v_j, kept
 // unnormalised (x_0 = v_0, the start vector); sigma_j = 1 / beta_{j-1}.
@@ -2305,7 +2557,7 @@ __global__ void sum_partials(const double *partials, int nblk, int width, double
 #define SQ_ALL_CUBES X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29) X(31) X(33) X(35) X(37)
 
 #ifndef SQ_COMMON_ONLY
-// Launch helpers.  Resident cubes (up to kResidentCube) run the register-ring
+// kernels in FP64 and moments_mixed_kernel in FP32-mixed mode, built for
 // kernels in FP64 and moments_kernel<c, float> in FP32-mixed mode, built for
 // 1, 2 or 4 projector chains.  Streamed cubes are built with two chains only
 // (the host rejects deeper sphere overlaps there) and run the FP64 streamed
@@ -2340,7 +2592,7 @@ hipError_t launch_moments_t(const LaunchArgs &a, int nch, bool mixed, int nwg, h
     return with_chains<c>(nch, [&](auto ncht) {
         constexpr int NCH = decltype(ncht)::value;
         if constexpr (!Shape<c>::STREAM) {
-            if (mixed) hipLaunchKernelGGL((moments_kernel<c, float, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            if (mixed) hipLaunchKernelGGL((moments_mixed_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
             else hipLaunchKernelGGL((moments_ring_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
         } else {
             hipLaunchKernelGGL((moments_kernel<c, double, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
@@ -2355,7 +2607,7 @@ hipError_t occupancy_t(bool lanczos, bool mixed, int nch, int *nb) {
         constexpr int NCH = decltype(ncht)::value;
         if constexpr (!Shape<c>::STREAM) {
             if (lanczos) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_ring_kernel<c, NCH>, B, 0);
-            if (mixed) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, float, NCH>, B, 0);
+            if (mixed) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_mixed_kernel<c, NCH>, B, 0);
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_ring_kernel<c, NCH>, B, 0);
         } else {
             if (lanczos) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, NCH>, B, 0);
