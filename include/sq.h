@@ -158,6 +158,21 @@ int sq_fermi_level(sq_ctx *ctx, const double *moments, double n_electrons, doubl
 int sq_density_energy(sq_ctx *ctx, const double *moments, double mu, double *rho,
                       double *energies, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as sq_density_energy, with the same arguments and synchronisation,
+ * computed without the context's quadrature-weight and reduction buffers.
+ * The per-node weights are formed in registers from moments and the
+ * coefficient table, and the reduction partials and sums live in a fixed
+ * library-owned device array (a static __device__ array of 3 * 1024 + 4
+ * doubles, about 24 KiB, one per GPU, held until the process ends; its size
+ * does not depend on the cell).  The call allocates nothing.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other host
+ * threads or streams) race and must be serialised by the caller.  rho may
+ * differ from sq_density_energy's only by rounding. */
+int sq_density_energy_static(sq_ctx *ctx, const double *moments, double mu, double *rho,
+                             double *energies, void *stream);
+
 /* Release the host tables (never touches caller-owned device memory). */
 void sq_destroy(sq_ctx *ctx);
 

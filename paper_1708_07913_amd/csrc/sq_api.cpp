@@ -1036,6 +1036,41 @@ int sq_density_energy(sq_ctx *c, const double *moments, double mu, double *rho, 
     });
 }
 
+int sq_density_energy_static(sq_ctx *c, const double *moments, double mu, double *rho, double *energies,
+                             void *stream) {
+    return guarded([&]() -> int {
+        int rc = check_ctx(c, kBounds);
+        if (rc) return rc;
+        if (!moments || !rho || !energies) return fail(SQ_EINVAL, "moments, rho (device) and energies (host) are required");
+        if (!is_finite(mu)) return fail(SQ_EINVAL, "mu must be finite");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        double *scratch = nullptr;
+        size_t bytes = 0;
+        rc = hip_check(sq::static_scratch(&scratch, &bytes), "static scratch address");
+        if (rc) return rc;
+        // the partials of at most 1024 reduction blocks and three sums: the
+        // fixed scratch holds them for any cell size
+        if (bytes < sizeof(double) * (3 * 1024 + 4))
+            return fail(SQ_ENOMEM, "static scratch smaller than the reduction needs");
+        double *sums = nullptr;
+        const double h3 = c->h * c->h * c->h;
+        rc = hip_check(sq::launch_density_static(moments, c->at<double>(c->off_ctab), c->at<double>(c->off_chi),
+                                                 c->at<double>(c->off_zeta), c->at<double>(c->off_rk), c->nd, c->nq,
+                                                 mu, c->kT, h3, rho, scratch, &sums, s),
+                       "density (static scratch)");
+        if (rc) return rc;
+        double v[3];
+        rc = hip_check(hipMemcpyAsync(v, sums, sizeof(v), hipMemcpyDeviceToHost, s), "reading device sums");
+        if (!rc) rc = hip_check(hipStreamSynchronize(s), "density (static scratch)");
+        if (rc) return rc;
+        energies[0] = v[0];
+        energies[1] = v[1];
+        energies[2] = v[0] + v[1];
+        energies[3] = h3 * v[2];
+        return SQ_OK;
+    });
+}
+
 void sq_destroy(sq_ctx *c) { delete c; }
 
 void sq_batch_default_options(sq_batch_options *opt) {

@@ -253,6 +253,15 @@ hipError_t launch_count(const double *W, const double *chi, const double *zeta, 
 hipError_t launch_density(const double *W, const double *chi, const double *zeta, const double *rk,
                           long long nd, int nq, double mu, const double *mu_dev, double kT, double h3,
                           double *rho, double *partials, int nblk, double *out, hipStream_t s);
+// Allocation-free density and energies: kernels use the library's static
+// device scratch (static_scratch: its device address on the current device,
+// looked up once per device, and its size).  *sums receives the device address
+// of {sum E_band terms, sum E_ent terms, sum rho}.
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(double **ptr, size_t *bytes);
+hipError_t launch_density_static(const double *mom, const double *ctab, const double *chi, const double *zeta,
+                                 const double *rk, long long nd, int nq, double mu, double kT, double h3,
+                                 double *rho, double *scratch_ptr, double **sums, hipStream_t s);
 // Batched Fermi level: N(mu_eval) of every snapshot still iterating (grid
 // nblk x nsnap, the same per-snapshot partial sums as launch_count), then one
 // Brent step per snapshot.

@@ -27,6 +27,7 @@
 
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 
 namespace sq {
@@ -2550,6 +2551,56 @@ __global__ void sum_partials(const double *partials, int nblk, int width, double
     }
 }
 
+// Density and energies straight from the moments, for the allocation-free
+// entry point: the quadrature weights W_qk = sum_j c-table[j][k] rho_q^j of a
+// node are formed in registers (same sums, same order as weights_kernel), so
+// no N_d x N_q buffer is needed.  Per-block partials go to `partials`.
+__global__ __launch_bounds__(kRedBlock) void density_direct_kernel(const double *mom, const double *ctab,
+                                                                   const double *chi, const double *zeta,
+                                                                   const double *rk, long long nd, int nq,
+                                                                   double mu, double kT, double h3, double *rho,
+                                                                   double *partials) {
+    __shared__ double sh[kRedBlock / 64];
+    double eb = 0.0, en = 0.0, er = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nd;
+         q += (long long)gridDim.x * blockDim.x) {
+        const double c = chi[q], z = zeta[q];
+        const double *r = mom + q * nq;
+        double sg = 0.0, sb = 0.0, se = 0.0;
+        for (int k = 0; k < nq; ++k) {
+            double w = 0.0;
+            for (int j = 0; j < nq; ++j) w += ctab[j * nq + k] * r[j];
+            const double lam = z * rk[k] + c;
+            const double x = (lam - mu) / kT;
+            const double g = fermi_fn(x);
+            sg += g * w;
+            sb += lam * g * w;
+            se += entropy_fn(x) * w;
+        }
+        const double rq = 2.0 / h3 * sg;
+        rho[q] = rq;
+        eb += 2.0 * sb;
+        en += 2.0 * kT * se;
+        er += rq;
+    }
+    const double a = block_reduce(eb, sh);
+    const double b = block_reduce(en, sh);
+    const double c = block_reduce(er, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = a;
+        partials[3 * blockIdx.x + 1] = b;
+        partials[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// Device scratch of the allocation-free density entry point: the per-block
+// partials of the reduction followed by the three reduced sums.  Its size does
+// not depend on the cell (the reduction uses at most kStaticBlocks blocks).
+// One copy per GPU, alive until the process ends.
+constexpr int kStaticBlocks = 1024;
+constexpr int kStaticScratchDoubles = 3 * kStaticBlocks + 4;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
 #endif  // common part
 
 }  // namespace
@@ -2760,6 +2811,41 @@ hipError_t launch_count_batch(const FermiSnap *fs, const BrentState *st, int nsn
 
 hipError_t launch_brent_feed(BrentState *st, const double *partials, int nblk, int nsnap, hipStream_t s) {
     hipLaunchKernelGGL(brent_feed_kernel, dim3((nsnap + 63) / 64), dim3(64), 0, s, st, partials, nblk, nsnap);
+    return hipGetLastError();
+}
+
+hipError_t static_scratch(double **ptr, size_t *bytes) {
+    // The device address of `scratch` on the current device.  In host code the
+    // array's name is not a device address; it is looked up once per device
+    // (hipGetSymbolAddress with that device current) and cached.
+    static std::mutex lock;
+    static double *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(lock);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double *>(p);
+    }
+    *ptr = addr[dev];
+    if (bytes) *bytes = sizeof(double) * kStaticScratchDoubles;
+    return hipSuccess;
+}
+
+hipError_t launch_density_static(const double *mom, const double *ctab, const double *chi, const double *zeta,
+                                 const double *rk, long long nd, int nq, double mu, double kT, double h3,
+                                 double *rho, double *scratch_ptr, double **sums, hipStream_t s) {
+    const int nblk = grid_for(nd, kRedBlock) < kStaticBlocks ? grid_for(nd, kRedBlock) : kStaticBlocks;
+    double *partials = scratch_ptr;
+    double *out = scratch_ptr + 3 * kStaticBlocks;
+    hipLaunchKernelGGL(density_direct_kernel, dim3(nblk), dim3(kRedBlock), 0, s, mom, ctab, chi, zeta, rk, nd, nq,
+                       mu, kT, h3, rho, partials);
+    hipLaunchKernelGGL(sum_partials, dim3(1), dim3(64), 0, s, partials, nblk, 3, out);
+    *sums = out;
     return hipGetLastError();
 }
 

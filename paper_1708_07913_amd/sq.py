@@ -65,6 +65,7 @@ def load_library():
     lib.sq_moments.argtypes = [P, P, P]
     lib.sq_fermi_level.argtypes = [P, P, D, dp, P]
     lib.sq_density_energy.argtypes = [P, P, D, P, dp, P]
+    lib.sq_density_energy_static.argtypes = [P, P, D, P, dp, P]
     lib.sq_destroy.argtypes = [P]
     lib.sq_destroy.restype = None
     lib.sq_batch_default_options.argtypes = [ct.POINTER(BatchOptions)]
@@ -80,6 +81,7 @@ def load_library():
     lib.sq_batch_destroy.restype = None
     for name in ("sq_setup", "sq_query", "sq_bind", "sq_update_veff", "sq_spectral_bounds",
                  "sq_set_bounds", "sq_moments", "sq_fermi_level", "sq_density_energy",
+                 "sq_density_energy_static",
                  "sq_batch_create", "sq_batch_query", "sq_batch_bind", "sq_batch_step",
                  "sq_batch_autotune", "sq_batch_tiles"):
         getattr(lib, name).restype = ct.c_int
@@ -210,6 +212,14 @@ class SQ:
         e = (ct.c_double * 4)()
         _check(_lib.sq_density_energy(self._ctx, _dptr(moments), float(mu), _dptr(rho), e,
                                       self._stream_ptr()))
+        return rho, np.array(list(e))
+
+    def density_energy_static(self, moments, mu, rho):
+        """sq_density_energy_static: the allocation-free variant; rho must be
+        a caller-allocated device tensor of N_d FP64."""
+        e = (ct.c_double * 4)()
+        _check(_lib.sq_density_energy_static(self._ctx, _dptr(moments), float(mu), _dptr(rho), e,
+                                             self._stream_ptr()))
         return rho, np.array(list(e))
 
     def scf_pass(self, n_electrons):
