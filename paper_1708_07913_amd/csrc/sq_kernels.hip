@@ -126,7 +126,7 @@ struct Lds {
     double img_coef[kMaxImages];
     double s[2][kMaxImages];
     double cs[kMaxImages];
-    double red[Shape<C>::NW * 2];
+    double red[Shape<C>::NW * 4];
     double bc[4];
     int scan_tot[Shape<C>::NW];
     int ni;
@@ -1451,40 +1451,28 @@ __device__ __forceinline__ void chainsd_advance(ChainD<UP> (&ch)[NCH], double *s
     }
 }
 
-// Sum of four values over the workgroup, returned to every thread.
-template <int C, typename T, int NCH>
-__device__ __forceinline__ void block_sum4(Lds<C, T, NCH> &L, double (&v)[4], int tid) {
+// Sum of N <= 4 values over the workgroup with a single barrier: every
+// thread adds the per-wave sums itself, in the same order (the results are
+// identical across threads).  The per-wave slots are not written again
+// before the caller's next barrier, so no trailing barrier is needed.
+template <int N, int C, typename T, int NCH>
+__device__ __forceinline__ void block_sum_once(Lds<C, T, NCH> &L, double (&v)[N], int tid) {
     constexpr int NW = Shape<C>::NW;
+    static_assert(N <= 4, "per-wave reduction slots");
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+    for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
     const int w = tid >> 6;
-    __syncthreads();
-    // red holds two doubles per wave: two rounds of two values
     if ((tid & 63) == 0) {
-        L.red[2 * w] = v[0];
-        L.red[2 * w + 1] = v[1];
-    }
-    __syncthreads();
-    if (tid < 2) {
-        double s = 0.0;
-        for (int i = 0; i < NW; ++i) s += L.red[2 * i + tid];
-        L.bc[tid] = s;
-    }
-    __syncthreads();
-    if ((tid & 63) == 0) {
-        L.red[2 * w] = v[2];
-        L.red[2 * w + 1] = v[3];
-    }
-    __syncthreads();
-    if (tid < 2) {
-        double s = 0.0;
-        for (int i = 0; i < NW; ++i) s += L.red[2 * i + tid];
-        L.bc[2 + tid] = s;
+#pragma unroll
+        for (int i = 0; i < N; ++i) L.red[N * w + i] = v[i];
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = uniform(L.bc[i]);
-    __syncthreads();
+    for (int i = 0; i < N; ++i) {
+        double acc = 0.0;
+        for (int ww = 0; ww < NW; ++ww) acc += L.red[N * ww + i];
+        v[i] = uniform(acc);
+    }
 }
 
 // y legs of plane z for all RB columns, own rows from the ring.
@@ -1718,31 +1706,37 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_ring_kernel(LaunchArg
         st.c0 = uniform(kin0 - chi);
         // one step; the ring layout alternates, so steps are taken in (up, down)
         // pairs and every pass of the loop starts in the upward layout
+        // projector coefficients of step 0 (t^1 = Hhat t^0)
+        for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK)
+            L.cs[i] = i < ni ? invz * L.img_coef[i] * L.s[cur][i] : 0.0;
+        __syncthreads();
         auto step = [&](int k, auto up) {
             constexpr bool UP = decltype(up)::value;
             st.al = k == 0 ? 1.0 : 2.0;
             st.k = k;
             st.prev = k > 0;
-            const double scale = uniform(st.al * invz);
-            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK)
-                L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur][i] : 0.0;
-            __syncthreads();
-            double d1 = 0.0, d2 = 0.0;
+            double d[2] = {0.0, 0.0};
             moments_ring_sweep<C, NCH, UP>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st, L.s[cur ^ 1], nch,
-                                           centre_r, mrow, d1, d2);
-            block_sum2(L, d1, d2, tid);
+                                           centre_r, mrow, d[0], d[1]);
+            // the sweep ended on a barrier: the dots of t^{k+1} are complete.
+            // Coefficients of the next step, and its dot accumulator cleared;
+            // the reduction's barrier publishes both.
+            const double scale = uniform(2.0 * invz);
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) {
+                L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur ^ 1][i] : 0.0;
+                L.s[cur][i] = 0.0;
+            }
+            block_sum_once<2>(L, d, tid);
             if (k + 1 > half / 2) {
                 if (tid == 0) {
-                    const double r2k = 2.0 * d1 - 1.0, r2k1 = 2.0 * d2 - L.bc[2];
+                    const double r2k = 2.0 * d[0] - 1.0, r2k1 = 2.0 * d[1] - L.bc[2];
                     mrow[2 * (k + 1)] = r2k;
                     mrow[2 * (k + 1) - 1] = r2k1;
                     if (fabs(r2k) > 1.0 + A.bounds_tol || fabs(r2k1) > 1.0 + A.bounds_tol)
                         atomicOr(A.flags, kFlagBounds);
                 }
             }
-            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) L.s[cur][i] = 0.0;
             cur ^= 1;
-            __syncthreads();
         };
         // n_pl is a multiple of 4: the number of steps, n_pl / 2, is even
         for (int k = 0; k < half; k += 2) {
@@ -1920,29 +1914,36 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_mixed_kernel(LaunchAr
         MomentsStep st;
         st.invz = invz;
         st.c0 = uniform(kin0 - chi);
+        // projector coefficients of step 0 (t^1 = Hhat t^0)
+        for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK)
+            L.cs[i] = i < ni ? invz * L.img_coef[i] * L.s[cur][i] : 0.0;
+        __syncthreads();
         auto begin_step = [&](int k) {
             st.al = k == 0 ? 1.0 : 2.0;
             st.k = k;
             st.prev = k > 0;
-            const double scale = uniform(st.al * invz);
-            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK)
-                L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur][i] : 0.0;
-            __syncthreads();
         };
+        // after a sweep (which ends on a barrier): the next step's projector
+        // coefficients and cleared dot accumulator, published by the
+        // reduction's barrier
         auto end_step = [&](int k, double d1, double d2) {
-            block_sum2(L, d1, d2, tid);
+            const double scale = uniform(2.0 * invz);
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) {
+                L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur ^ 1][i] : 0.0;
+                L.s[cur][i] = 0.0;
+            }
+            double d[2] = {d1, d2};
+            block_sum_once<2>(L, d, tid);
             if (k + 1 > half / 2) {
                 if (tid == 0) {
-                    const double r2k = 2.0 * d1 - 1.0, r2k1 = 2.0 * d2 - mrow[1];
+                    const double r2k = 2.0 * d[0] - 1.0, r2k1 = 2.0 * d[1] - mrow[1];
                     mrow[2 * (k + 1)] = r2k;
                     mrow[2 * (k + 1) - 1] = r2k1;
                     if (fabs(r2k) > 1.0 + A.bounds_tol || fabs(r2k1) > 1.0 + A.bounds_tol)
                         atomicOr(A.flags, kFlagBounds);
                 }
             }
-            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) L.s[cur][i] = 0.0;
             cur ^= 1;
-            __syncthreads();
         };
         // FP64 phase on the ring; t^{k-1} in the slot
         {
@@ -2244,11 +2245,19 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_ring_kernel(LaunchArg
             double dots[4];
             lanczos_ring_sweep<C, NCH, UP>(A, L, cl, R, rda, rdb, vr, pvr, vcol, voff, zbase, kw, kin0, st,
                                            L.s[cur ^ 1], nch, dots);
-            // sum_I c_I s_I(x_j)^2 (the sweep ended on a barrier: every run is closed)
+            // the sweep ended on a barrier: every run is closed.  sum_I c_I
+            // s_I(x_j)^2, the next formation's coefficients c_I s_I(x_j) and a
+            // cleared accumulator for its dots (published by the reduction's
+            // barrier)
             double dimg = 0.0;
-            for (int i = fresh_tid(); i < ni; i += S::BLOCK) dimg += L.img_coef[i] * L.s[cur ^ 1][i] * L.s[cur ^ 1][i];
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) {
+                const double sj = L.s[cur ^ 1][i];
+                if (i < ni) dimg += L.img_coef[i] * sj * sj;
+                L.cs[i] = i < ni ? L.img_coef[i] * sj : 0.0;
+                L.s[cur][i] = 0.0;
+            }
             dots[3] = dimg;
-            block_sum4(L, dots, tid);
+            block_sum_once<4>(L, dots, tid);
             double sig = 1.0;
             if (j >= 1) {
                 const double be = uniform(sqrt(dots[1]));  // beta_{j-1}
@@ -2271,16 +2280,10 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_ring_kernel(LaunchArg
                 if (!isfinite(al)) atomicOr(A.flags, kFlagLanczos);
             }
             if (j == kmax - 1) return false;
-            // coefficients of the next formation: cs = c_I s_I(x_j)
-            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) {
-                L.cs[i] = i < ni ? L.img_coef[i] * L.s[cur ^ 1][i] : 0.0;
-                L.s[cur][i] = 0.0;
-            }
             cur ^= 1;
             sig_m2 = sig_m1;
             sig_m1 = sig;
             al_m1 = al;
-            __syncthreads();
             return true;
         };
         for (int j = 0; j < kmax; j += 2) {
