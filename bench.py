@@ -214,6 +214,17 @@ def run_ensemble(args):
     torch.cuda.synchronize()
     reuse_s = time.perf_counter() - t1
     del br
+    # the same pass with the default tiles (32 nodes per item, occupancy-limited
+    # workgroups per CU), for the autotuner's gain
+    bd = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=True)
+    bd.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bd.step()
+    torch.cuda.synchronize()
+    default_s = time.perf_counter() - t1
+    default_tiles = bd.tiles()
+    del bd
     node_steps = sum(g.nd * (wl.npl // 2) for g, wl in zip(snaps, wls))
     nodes = sum(g.nd for g in snaps)
     rec = {"metric": METRIC, "value": node_steps / (wall / args.steps), "unit": "grid-pt*Chebyshev-steps/s",
@@ -225,7 +236,7 @@ def run_ensemble(args):
                       "cubes": sorted({2 * g.m + 1 for g in snaps}), "npl": sorted({wl.npl for wl in wls}),
                       "parallelism": "single GPU", "batch": "one persistent launch per cube size, hipGraph"},
            "s_per_scf": wall / args.steps, "s_per_scf_reusing_bounds": reuse_s, "tiles": tiles,
-           "autotune_s": tune_s,
+           "autotune_s": tune_s, "s_per_scf_default_tiles": default_s, "default_tiles": default_tiles,
            "electron_count_err_max": float(max(abs(e[i][3] - wl.n_electrons) for i, wl in enumerate(wls)))}
     if prec == sq.FP32_MIXED:
         # error of the mixed recurrence per snapshot, against the FP64 path on the

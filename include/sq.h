@@ -230,7 +230,8 @@ int sq_batch_bind(sq_batch *batch, void *workspace, size_t bytes, void *stream);
 int sq_batch_step(sq_batch *batch, double *mu, double *energies, void *stream);
 
 /* Time the candidate tile shapes (block_nodes x wg_per_cu) on a sample of
- * every snapshot's nodes and keep the fastest; with cache_path (host, may be
+ * every snapshot's nodes (the first eighth; Lanczos and moments launches
+ * together) and keep the fastest; with cache_path (host, may be
  * NULL) the choice is read from / appended to that JSON file, keyed by the
  * device and the batch's cube sizes and precision.  Invalidates a captured
  * graph.  Synchronises `stream`. */

@@ -692,7 +692,8 @@ std::string tune_key(const sq_batch *b) {
         parts.push_back("C" + std::to_string(g.C) + "x" + std::to_string(g.nch) + ":" + std::to_string(nodes));
     }
     std::sort(parts.begin(), parts.end());
-    std::string key = std::string(b->device_name) + "/" + std::to_string(b->cus) + "cu/" + (b->mixed ? "mixed" : "fp64");
+    // "lm": timed on the Lanczos and moments launches together
+    std::string key = std::string(b->device_name) + "/" + std::to_string(b->cus) + "cu/lm/" + (b->mixed ? "mixed" : "fp64");
     for (const auto &p : parts) key += "/" + p;
     return key;
 }
@@ -1295,13 +1296,10 @@ int sq_batch_autotune(sq_batch *b, const char *cache_path, void *stream) {
         const std::string key = tune_key(b);
         int best_block = 0, best_wg = 0;
         if (!cache_lookup(cache_path, key, &best_block, &best_wg)) {
-            // spectral bounds of every node first (the moments need them)
             rc = upload_args(b, b->own);
-            if (!rc) rc = enqueue_recurrences(b, true, false, b->own);
-            if (!rc) rc = hip_check(hipStreamSynchronize(b->own), "autotune bounds");
             if (rc) return rc;
             int max_occ = 1;
-            for (const auto &g : b->groups) max_occ = std::max(max_occ, g.occ_m);
+            for (const auto &g : b->groups) max_occ = std::max({max_occ, g.occ_l, g.occ_m});
             std::vector<int> wgs = {1};
             if (max_occ > 1) wgs.push_back(max_occ);
             hipEvent_t e0, e1;
@@ -1309,14 +1307,16 @@ int sq_batch_autotune(sq_batch *b, const char *cache_path, void *stream) {
             if (!rc) rc = hip_check(hipEventCreate(&e1), "autotune events");
             if (rc) return rc;
             double best_ms = 1e300;
-            // a sample of every snapshot: its first 1/8 of the nodes
+            // a sample of every snapshot (its first 1/8 of the nodes) through
+            // both recurrence kernels: Lanczos (which also gives the sample's
+            // bounds) and the moments
             for (int block : {8, 32, 128}) {
                 for (int wg : wgs) {
                     build_items(b, block, 0.125);
                     b->wg_per_cu = wg;
                     rc = upload_items(b, b->own);
                     if (!rc) rc = hip_check(hipEventRecord(e0, b->own), "autotune timing");
-                    if (!rc) rc = enqueue_recurrences(b, false, true, b->own);
+                    if (!rc) rc = enqueue_recurrences(b, true, true, b->own);
                     if (!rc) rc = hip_check(hipEventRecord(e1, b->own), "autotune timing");
                     if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune timing");
                     float ms = 0.f;
