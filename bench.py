@@ -23,12 +23,18 @@ import time
 
 import numpy as np
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "SQ grid-pt*Chebyshev-steps/s & s/SCF iter, FP64 vs FP32-mixed at rho err 1e-5"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1708_07913_amd", "csrc", "sq_kernels.hip")
+
+
+def log(msg: str) -> None:
+    """Progress line on stderr, with seconds since the bench started."""
+    print(f"[bench {time.perf_counter() - T_START:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
@@ -103,9 +109,13 @@ def run_gpu(wl, steps, warmup, precision):
     V = torch.from_numpy(wl.veff()).cuda()
     g = sq.SQ.from_workload(wl, veff=V, precision=precision)
     stream = torch.cuda.current_stream()
-    for _ in range(warmup):
+    tag = "fp64" if precision == sq.FP64 else "mixed"
+    log(f"{tag}: context ready, {warmup} warm-up pass(es)")
+    for w in range(warmup):
         g.scf_pass(wl.n_electrons)
+        log(f"{tag}: warm-up {w + 1}/{warmup} done")
     torch.cuda.synchronize()
+    log(f"{tag}: {steps} timed pass(es)")
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
     out = None
     t0 = time.perf_counter()
@@ -121,6 +131,9 @@ def run_gpu(wl, steps, warmup, precision):
         rho, en = g.density_energy(mom, mu)
         e[4].record(stream)
         out = (bounds, mom, mu, rho, en)
+        # the Fermi search has read back its counts, so this step's moments
+        # are done; a line per step shows progress on long runs
+        log(f"{tag}: step {s + 1}/{steps} mu {mu:.12f}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     phases = np.array([[ev[s][i].elapsed_time(ev[s][i + 1]) for i in range(4)] for s in range(steps)])
@@ -196,7 +209,7 @@ def run_ensemble(args):
     t0 = time.perf_counter()
     tiles = b.autotune(cache)
     tune_s = time.perf_counter() - t0
-    print(f"[bench] ensemble: tiles {tiles} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
+    log(f"ensemble: tiles {tiles} ({tune_s:.1f} s)")
     for _ in range(args.warmup):
         b.step()
     torch.cuda.synchronize()
@@ -253,7 +266,7 @@ def run_ensemble(args):
             errs.append({"snapshot": wl.name, "rho_max_rel_err": float(np.abs(rm - r64).max() / r64.max()),
                          "E_band_err_Ha_per_atom": float(abs(em[0] - e64[0]) / wl.natom),
                          "F_err_Ha_per_atom": float(abs(em[2] - e64[2]) / wl.natom)})
-            print(f"[bench] {wl.name}: mixed rho err {errs[-1]['rho_max_rel_err']:.2e}", file=sys.stderr, flush=True)
+            log(f"{wl.name}: mixed rho err {errs[-1]['rho_max_rel_err']:.2e}")
             del g64, mom64, rho64, rhom
         rec["mixed_vs_fp64"] = {"rho_max_rel_err": max(x["rho_max_rel_err"] for x in errs),
                                 "E_band_err_Ha_per_atom": max(x["E_band_err_Ha_per_atom"] for x in errs),
@@ -289,7 +302,7 @@ def run_mixed_sweep():
                          "E_band_err_Ha_per_atom": float(abs(e[0] - e64[0]) / wl.natom),
                          "F_err_Ha_per_atom": float(abs(e[2] - e64[2]) / wl.natom),
                          "electron_count_err": float(abs(e[3] - e64[3]))})
-            print(f"[bench] mixed sweep kT={kT} npl={npl}: {rows[-1]}", file=sys.stderr, flush=True)
+            log(f"mixed sweep kT={kT} npl={npl}: {rows[-1]}")
     print(json.dumps({"workload": "al4_h0.5_rc2.5 mixed-precision sweep", "reference": "FP64 GPU path",
                       "rows": rows, "max_rho_rel_err": max(x["rho_max_rel_err"] for x in rows)}), flush=True)
 
@@ -337,8 +350,9 @@ def main():
                     choices=["large", "paper", "paper-small", "tiny", "ensemble", "mixed-sweep"])
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"],
                     help="precision of the ensemble workload")
-    ap.add_argument("--mixed-steps", type=int, default=1,
-                    help="timed FP32-mixed passes (after one untimed one)")
+    ap.add_argument("--mixed-steps", type=int, default=1, help="timed FP32-mixed passes")
+    ap.add_argument("--mixed-warmup", type=int, default=0,
+                    help="untimed FP32-mixed passes (its Lanczos launch is the FP64 one, already warm)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -352,6 +366,7 @@ def main():
 
     import torch
     from paper_1708_07913_amd import sq
+    log("torch imported")
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
@@ -364,7 +379,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        print("[bench] copy calibration: 1 GiB device-to-device", file=sys.stderr, flush=True)
+        log("copy calibration: 1 GiB device-to-device")
     if args.workload == "ensemble":
         run_ensemble(args)
         return
@@ -372,7 +387,7 @@ def main():
         run_mixed_sweep()
         return
     wl = workload(args.workload)
-    print(f"[bench] {wl.name}: n={wl.n} natom={wl.natom} npl={wl.npl}", file=sys.stderr, flush=True)
+    log(f"{wl.name}: n={wl.n} natom={wl.natom} npl={wl.npl}")
 
     g, (bounds, mom, mu, rho, en), wall, ph = run_gpu(wl, args.steps, args.warmup, sq.FP64)
     nd, S = g.nd, wl.npl // 2
@@ -380,9 +395,10 @@ def main():
     ns = C ** 3
     ms_step = 1e3 * wall / args.steps
     value = nd * S / (wall / args.steps)
-    print(f"[bench] fp64: {ms_step:.1f} ms/step phases(ms) bounds {ph[0]:.1f} moments {ph[1]:.1f} "
-          f"fermi {ph[2]:.1f} density {ph[3]:.1f}", file=sys.stderr, flush=True)
+    log(f"fp64: {ms_step:.1f} ms/step phases(ms) bounds {ph[0]:.1f} moments {ph[1]:.1f} "
+          f"fermi {ph[2]:.1f} density {ph[3]:.1f}")
     reuse_s = reuse_pass(g, bounds, wl.n_electrons)
+    log(f"pass reusing bounds: {reuse_s:.2f} s")
 
     # dominant kernel and its roofline (algorithmic bytes: 3 N_s words per node-step)
     lanczos_bytes = nd * 50 * 3 * ns * 8
@@ -425,8 +441,9 @@ def main():
 
     gm = None
     if not args.no_mixed:
-        gm, (_, _, _, _, en_m), wall_m, ph_m = run_gpu(wl, args.mixed_steps, 1, sq.FP32_MIXED)
-        rec["mixed"] = {"steps": args.mixed_steps, "warmup": 1,
+        gm, (_, _, _, _, en_m), wall_m, ph_m = run_gpu(wl, args.mixed_steps, args.mixed_warmup,
+                                                        sq.FP32_MIXED)
+        rec["mixed"] = {"steps": args.mixed_steps, "warmup": args.mixed_warmup,
                         "ms_per_step": 1e3 * wall_m / args.mixed_steps,
                         "value": nd * S / (wall_m / args.mixed_steps),
                         "moments_node_steps_per_s": nd * S / (ph_m[1] * 1e-3),
@@ -434,7 +451,7 @@ def main():
                                      "density": ph_m[3]},
                         "electron_count_err": float(abs(en_m[3] - wl.n_electrons))}
         roof_meas["moments_mixed"] = stencil_roofline(moments_bytes // 2, S * flops_step, ph_m[1] * 1e-3, bw)
-        print(f"[bench] mixed: {rec['mixed']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+        log(f"mixed: {rec['mixed']['ms_per_step']:.1f} ms/step")
 
     path = golden_path(wl)
     if path and not args.no_accuracy:
@@ -442,10 +459,11 @@ def main():
         if gm is not None:
             acc["mixed"] = accuracy_vs_oracle(wl, gm, path)
         rec["accuracy_vs_oracle"] = acc
-        print(f"[bench] accuracy vs oracle: {json.dumps(acc)}", file=sys.stderr, flush=True)
+        log(f"accuracy vs oracle: {json.dumps(acc)}")
 
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)
+        log(f"cpu baseline: {rec['cpu_baseline']['sample']}")
     print(json.dumps(rec), flush=True)
 
 
