@@ -403,10 +403,13 @@ def main():
     # dominant kernel and its roofline (algorithmic bytes: 3 N_s words per node-step)
     lanczos_bytes = nd * 50 * 3 * ns * 8
     moments_bytes = nd * S * 3 * ns * 8
+    # cubes up to 31 points run the register-ring kernels, wider ones the
+    # streamed kernels
+    ring = "_ring" if C <= 31 else ""
     if ph[0] >= ph[1]:
-        kname, kbytes, kms = "lanczos_kernel", lanczos_bytes, ph[0]
+        kname, kbytes, kms = f"lanczos{ring}_kernel", lanczos_bytes, ph[0]
     else:
-        kname, kbytes, kms = "moments_kernel", moments_bytes, ph[1]
+        kname, kbytes, kms = f"moments{ring}_kernel", moments_bytes, ph[1]
     achieved = kbytes / (kms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kname, wl.name),
