@@ -228,7 +228,7 @@ int stage_launch(sq_ctx *c, const sq::RecurrenceArgs &a, int which, hipStream_t 
     k->slots = c->ws + c->off_slots;
     k->wslots = c->ws + c->off_wslots;
     k->xslots = c->ws + c->off_xslots;
-    k->slot_elems = c->ns;
+    k->slot_elems = sq::slot_elems_for(c->C);
     return SQ_OK;
 }
 
@@ -279,12 +279,14 @@ void layout(sq_ctx *c) {
     c->off_flags = take(64);
     c->off_args = take(2 * sizeof(sq::RecurrenceArgs));
     c->off_v32 = take(c->opt.precision == SQ_FP32_MIXED ? size_t(c->nd) * sizeof(float) : 0);
-    c->off_slots = take(size_t(c->nwg_slots) * size_t(c->ns) * sizeof(double));
+    // one slot per workgroup: C planes of slot_plane(C) doubles
+    const size_t se = size_t(sq::slot_elems_for(c->C));
+    c->off_slots = take(size_t(c->nwg_slots) * se * sizeof(double));
     // streamed regions (wider than kResidentCube) need a second buffer in the
     // moments sweep and a third in Lanczos
     const bool stream = c->C > sq::kResidentCube;
-    c->off_wslots = take(size_t(stream ? c->nwg_slots : c->nwg_lanczos) * size_t(c->ns) * sizeof(double));
-    c->off_xslots = take(stream ? size_t(c->nwg_lanczos) * size_t(c->ns) * sizeof(double) : 0);
+    c->off_wslots = take(size_t(stream ? c->nwg_slots : c->nwg_lanczos) * se * sizeof(double));
+    c->off_xslots = take(stream ? size_t(c->nwg_lanczos) * se * sizeof(double) : 0);
     c->total = off;
 }
 
@@ -358,7 +360,7 @@ struct sq_batch {
     int device = 0, cus = 0, max_brent = 200;
     char device_name[256] = {0};
     std::vector<Group> groups;
-    long long max_ns = 0;
+    long long max_slot = 0;          // largest workgroup slot (doubles) of any snapshot
     int nwg_cap = 0;                 // largest grid of any launch (buffers are sized for it)
     int block_nodes = 32, wg_per_cu = 0;
     std::vector<sq::WorkItem> items;
@@ -467,7 +469,7 @@ sq::LaunchArgs group_launch(sq_batch *b, const sq_batch::Group &g, int counter) 
     k.slots = b->ws + b->off_slots;
     k.wslots = b->ws + b->off_wslots;
     k.xslots = b->ws + b->off_xslots;
-    k.slot_elems = b->max_ns;
+    k.slot_elems = b->max_slot;
     return k;
 }
 
@@ -673,7 +675,7 @@ int batch_layout(sq_batch *b) {
     for (sq_ctx *c : b->ctx) vtot += size_t(c->nd);
     b->off_vref = take(vtot * sizeof(double));
     b->off_red = take(2 * n * sizeof(double));
-    const size_t slot = size_t(b->nwg_cap) * size_t(b->max_ns) * sizeof(double);
+    const size_t slot = size_t(b->nwg_cap) * size_t(b->max_slot) * sizeof(double);
     bool stream = false;
     for (const auto &g : b->groups) stream = stream || g.C > sq::kResidentCube;
     b->off_slots = take(slot);
@@ -1112,7 +1114,7 @@ int sq_batch_create(sq_batch **out, sq_ctx *const *ctxs, int n, double *const *m
             b->rho.push_back(rho[i]);
             b->n_e.push_back(n_electrons[i]);
             b->max_brent = i == 0 ? c->opt.max_brent : std::max(b->max_brent, c->opt.max_brent);
-            b->max_ns = std::max(b->max_ns, c->ns);
+            b->max_slot = std::max(b->max_slot, sq::slot_elems_for(c->C));
             // one launch per cube side and chain count
             auto g = std::find_if(b->groups.begin(), b->groups.end(),
                                   [&](const sq_batch::Group &x) { return x.C == c->C && x.nch == c->nch; });

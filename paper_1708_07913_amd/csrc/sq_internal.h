@@ -14,6 +14,30 @@ constexpr int kMaxLanczos = 256; // Lanczos steps per node
 constexpr int kMaxCube = 37;     // largest cube side (region of influence)
 constexpr int kResidentCube = 31; // largest cube side whose columns stay in registers
 
+// Rows of the cube owned by one thread of the recurrence kernels: one column
+// up to 27 points (a workgroup of C^2 threads, 7-12 waves for 21-27 points),
+// two y-adjacent columns for 29 and 31 points (512-thread workgroups, 256
+// VGPRs per lane; the pair shares its y-neighbour reads), three beyond 31
+// points.  Two rows on the 21-27-point cubes leave one wave per SIMD and run
+// 12-31 % slower; one row on 29 points spills.
+constexpr int rows_per_thread(int C) { return C > kResidentCube ? 3 : (C >= 29 ? 2 : 1); }
+// Threads per row group (lanes along x): 29- and 31-point cubes give each row
+// group 32 lanes, the last ones idle.
+constexpr int row_group_threads(int C) { return (C == 29 || C == 31) ? 32 : C; }
+// Doubles per plane of a workgroup's recurrence slot.  The Lanczos ring
+// kernel (cubes up to kResidentCube) stores plane z of a vector thread by
+// thread, element z * slot_plane + t * rows + r for row r of thread t, so that
+// a thread moves all its rows with one 8- or 16-byte access.  The moments
+// kernels and the streamed kernels store the cube's plane, element
+// z * C^2 + y * C + x, which fits as slot_plane >= C^2.
+constexpr long long slot_plane(int C) {
+    return C > kResidentCube
+               ? (long long)C * C
+               : (long long)row_group_threads(C) * ((C + rows_per_thread(C) - 1) / rows_per_thread(C)) *
+                     rows_per_thread(C);
+}
+constexpr long long slot_elems_for(int C) { return (long long)C * slot_plane(C); }
+
 // One atom's projector, stored as z-runs: for every (dx, dy) column of the
 // sphere relative to the base node (bx, by, bz) = floor(R / h), the contiguous
 // range dz0 .. dz0 + len - 1 of grid points inside the sphere.

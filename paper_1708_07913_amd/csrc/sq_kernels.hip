@@ -53,14 +53,6 @@ constexpr int kMixedFp64Steps = 4;
 constexpr int kRingPlanesPerBarrier = SQ_RING_PPB;  // 1 or 2 (four plane buffers)
 constexpr int kLanczosAhead = SQ_LANCZOS_AHEAD;
 
-// Rows of the cube owned by one thread: one column up to 27 points (a
-// workgroup of C^2 threads, 7-12 waves for 21-27 points), two y-adjacent
-// columns for 29 and 31 points (512-thread workgroups, 256 VGPRs per lane; the
-// pair shares its y-neighbour reads), three beyond 31 points.  Two rows on the
-// 21-27-point cubes leave one wave per SIMD and run 12-31 % slower; one row
-// on 29 points spills.
-constexpr int rows_per_thread(int C) { return C > kResidentCube ? 3 : (C >= 29 ? 2 : 1); }
-
 // Smallest row stride >= pe for which a step from (x = xw - 1, y) to
 // (x = 0, y + rb) moves the address by 1 modulo 32 (see Shape::P); the cube
 // side c is not needed beyond xw and pe.
@@ -79,8 +71,9 @@ struct Shape {
     // 29- and 31-point cubes give each row group 32 lanes (the last idle or
     // two): a half-wave then reads 32 consecutive plane entries, which keeps
     // the 64-bit LDS reads free of bank conflicts
-    static constexpr int XW = (C == 29 || C == 31) ? 32 : C;  // threads per row group
+    static constexpr int XW = row_group_threads(C);         // threads per row group
     static constexpr int NT = XW * YP;                       // threads owning row groups
+    static constexpr int SP = (int)slot_plane(C);            // doubles per slot plane
     static constexpr int PE = C + 2 * NO;                    // padded plane edge (zero halo NO)
     // Row stride of the plane.  With XW = C the lanes of a wave run along x
     // and step to the next row group at x = C; a stride with
@@ -172,6 +165,34 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsig
 }
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+// A thread's RB rows at one plane of a thread-interleaved slot (Lanczos ring
+// kernel): one 8- or 16-byte access per thread, so a wave moves one
+// contiguous, line-aligned block.  The moments ring kernel keeps one access
+// per row: with the paired access it spilled more and ran 21 % slower.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <int RB>
+__device__ __forceinline__ void slot_load(double (&v)[RB], __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    static_assert(RB == 1 || RB == 2, "one or two rows per thread");
+    if constexpr (RB == 1) {
+        v[0] = bload<double>(r, voff, soff);
+    } else {
+        const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        v[0] = __builtin_bit_cast(double, u32x2{q.x, q.y});
+        v[1] = __builtin_bit_cast(double, u32x2{q.z, q.w});
+    }
+}
+template <int RB>
+__device__ __forceinline__ void slot_store(const double (&v)[RB], __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                           unsigned soff) {
+    static_assert(RB == 1 || RB == 2, "one or two rows per thread");
+    if constexpr (RB == 1) {
+        bstore(v[0], r, voff, soff);
+    } else {
+        const u32x2 a = __builtin_bit_cast(u32x2, v[0]), b = __builtin_bit_cast(u32x2, v[1]);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{a.x, a.y, b.x, b.y}, r, voff, soff, 0);
+    }
 }
 
 // Keep a running sum materialised where it is updated.  Without this the
@@ -526,12 +547,14 @@ struct Cols {
     int corner;                 // LDS offset of the thread's neighbourhood corner
     int col[RB];                // cube column index, or -1
     int pcw[RB];                // LDS write offset of the column's plane value
+    unsigned slot;              // byte offset of the thread's rows in a slot plane (Lanczos ring)
     __device__ __forceinline__ void init(int tid) {
         const bool t_active = tid < S::NT;
         x = t_active ? tid % S::XW : 0;
         y0 = t_active ? (tid / S::XW) * RB : 0;
         // lanes past the cube's x range read (and discard) the next padded row
         corner = t_active ? y0 * S::P + x : S::IDLE_CORNER;
+        slot = (t_active && x < C && y0 < C) ? (unsigned)(tid * RB) * 8u : kIdleOffset;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const bool ok = t_active && (x < C) && (y0 + r < C);
@@ -2030,7 +2053,7 @@ __device__ __forceinline__ void lanczos_ring_sweep(const AT &A, Lds<C, double, N
                                                    __amdgpu_buffer_rsrc_t rda, __amdgpu_buffer_rsrc_t rdb,
                                                    __amdgpu_buffer_rsrc_t vr, __amdgpu_buffer_rsrc_t pvr,
                                                    const unsigned (&vcol)[Shape<C>::RB],
-                                                   const unsigned (&voff)[Shape<C>::RB], unsigned zbase,
+                                                   unsigned tslot, unsigned zbase,
                                                    const double (&kw)[NO + 1], double kin0, const LanczosStep &st,
                                                    double *snext, int nch, double (&dots)[4]) {
     using S = Shape<C>;
@@ -2044,38 +2067,36 @@ __device__ __forceinline__ void lanczos_ring_sweep(const AT &A, Lds<C, double, N
     unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
     asm volatile("" : "+s"(zb));
     // slots not yet written in this node are not read (their loads return 0)
-    unsigned aoff[RB], boff[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        aoff[r] = st.ra ? voff[r] : kIdleOffset;
-        boff[r] = st.rb ? voff[r] : kIdleOffset;
-    }
+    const unsigned aoff = st.ra ? tslot : kIdleOffset;
+    const unsigned boff = st.rb ? tslot : kIdleOffset;
     double an[FA][RB], bn[FA][RB];
 #pragma unroll
-    for (int f = 0; f < FA; ++f)
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            an[f][r] = 0.0;
-            bn[f][r] = 0.0;
-            if (f < C) {
-                const unsigned so = (unsigned)(D::plane(f, C) * S::CC) * 8u;
-                an[f][r] = bload<double>(rda, aoff[r], so);
-                bn[f][r] = bload<double>(rdb, boff[r], so);
-            }
+    for (int f = 0; f < FA; ++f) {
+        if (f < C) {
+            const unsigned so = (unsigned)(D::plane(f, C) * S::SP) * 8u;
+            slot_load<RB>(an[f], rda, aoff, so);
+            slot_load<RB>(bn[f], rdb, boff, so);
         }
+    }
     double da = 0.0, db = 0.0, de = 0.0;
     // formation of plane D::plane(f): x into the ring's input layout and the slot
     auto form = [&](int f) {
         const int z = D::plane(f, C);
-        const unsigned sz = (unsigned)(z * S::CC) * 8u;
+        const unsigned sz = (unsigned)(z * S::SP) * 8u;
+        double av[RB], bv[RB], xs[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const double a = an[f % FA][r], b = bn[f % FA][r];
-            if (f + FA < C) {
-                const unsigned so = (unsigned)(D::plane(f + FA, C) * S::CC) * 8u;
-                an[f % FA][r] = bload<double>(rda, aoff[r], so);
-                bn[f % FA][r] = bload<double>(rdb, boff[r], so);
-            }
+            av[r] = an[f % FA][r];
+            bv[r] = bn[f % FA][r];
+        }
+        if (f + FA < C) {
+            const unsigned so = (unsigned)(D::plane(f + FA, C) * S::SP) * 8u;
+            slot_load<RB>(an[f % FA], rda, aoff, so);
+            slot_load<RB>(bn[f % FA], rdb, boff, so);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const double a = av[r], b = bv[r];
             // step 0: fu = 1, fa = fb = 0 and no projector coefficients, so x_0
             // passes through unchanged
             double pu = R[r][z + D::IN];
@@ -2085,7 +2106,7 @@ __device__ __forceinline__ void lanczos_ring_sweep(const AT &A, Lds<C, double, N
             double x = st.fu * pu - st.fb * b - st.fa * a;
             if (!cl.valid(r)) x = 0.0;
             R[r][z + D::IN] = x;
-            bstore(x, rdb, voff[r], sz);  // x_j over x_{j-2}
+            xs[r] = x;
             db += x * x;
             de += x * a;
             pin(db);
@@ -2099,6 +2120,7 @@ __device__ __forceinline__ void lanczos_ring_sweep(const AT &A, Lds<C, double, N
             }
             chainsd_advance<UP, C, NCH>(ch[r], snext, L.runs, pvr, z, nch);
         }
+        slot_store<RB>(xs, rdb, tslot, sz);  // x_j over x_{j-2}
     };
 #pragma unroll
     for (int f = 0; f < NO && f < C; ++f) form(f);
@@ -2176,9 +2198,6 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_ring_kernel(LaunchArg
         make_rsrc(reinterpret_cast<double *>(K.slots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
     const __amdgpu_buffer_rsrc_t s1 =
         make_rsrc(reinterpret_cast<double *>(K.wslots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
-    unsigned voff[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * 8u : kIdleOffset;
     const long long ns = (long long)C * C * C;
 
     WorkSource work;
@@ -2243,7 +2262,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_ring_kernel(LaunchArg
             const __amdgpu_buffer_rsrc_t rda = (j & 1) ? s0 : s1;  // x_{j-1}
             const __amdgpu_buffer_rsrc_t rdb = (j & 1) ? s1 : s0;  // x_{j-2}, then x_j
             double dots[4];
-            lanczos_ring_sweep<C, NCH, UP>(A, L, cl, R, rda, rdb, vr, pvr, vcol, voff, zbase, kw, kin0, st,
+            lanczos_ring_sweep<C, NCH, UP>(A, L, cl, R, rda, rdb, vr, pvr, vcol, cl.slot, zbase, kw, kin0, st,
                                            L.s[cur ^ 1], nch, dots);
             // the sweep ended on a barrier: every run is closed.  sum_I c_I
             // s_I(x_j)^2, the next formation's coefficients c_I s_I(x_j) and a
