@@ -61,6 +61,7 @@ struct sq_ctx {
     int device = 0;
     int nwg_lanczos = 0, nwg_moments = 0, nwg_slots = 0;
     int nch = 2;        // projector chains per cube column (max sphere overlap depth)
+    int pstride = 0;    // doubles between a projector value and the one a plane above
     int max_overlap = 0;
     size_t off_atoms = 0, off_runs = 0, off_pvals = 0, off_chi = 0, off_zeta = 0, off_ctab = 0,
            off_rk = 0, off_W = 0, off_part = 0, off_scal = 0, off_flags = 0, off_v32 = 0,
@@ -100,12 +101,23 @@ void laplacian_weights(int no, double h, double *w) {
     }
 }
 
-// Projector of one atom as z-runs over (dx, dy) columns of its sphere.
-int build_atom_table(sq_ctx *c, const double *R, double sig, double rc, double gamma) {
+// Reach of an atom's projector sphere in grid steps from its base node: the
+// sphere's points have offsets -r .. r + 1 in each direction.
+int sphere_reach(double rc, double h) { return int(std::ceil(rc / h)) + 1; }
+
+// Projector of one atom as z-runs over (dx, dy) columns of its sphere.  The
+// values sit in a box of (2 rbox + 2)^3 doubles, x fastest and zero outside
+// the sphere, so that neighbouring columns of one plane are neighbours in
+// memory (a wave's loads of one plane coalesce); a run's value at the next
+// plane is c->pstride doubles further.
+int build_atom_table(sq_ctx *c, const double *R, double sig, double rc, double gamma, int rbox) {
     const double h = c->h;
     const int b[3] = {int(std::floor(R[0] / h)), int(std::floor(R[1] / h)), int(std::floor(R[2] / h))};
-    const int r = int(std::ceil(rc / h)) + 1;
+    const int r = sphere_reach(rc, h);
     const double rc2 = rc * rc;
+    const int W = 2 * rbox + 2;
+    if (size_t(c->pvals.size()) + size_t(W) * W * W > size_t(std::numeric_limits<int32_t>::max() / 2))
+        return fail(SQ_EINVAL, "projector tables too large");
     sq::AtomDev at{};
     at.bx = b[0];
     at.by = b[1];
@@ -116,6 +128,11 @@ int build_atom_table(sq_ctx *c, const double *R, double sig, double rc, double g
         at.dmax[k] = std::numeric_limits<int>::min();
     }
     const size_t v0 = c->pvals.size();
+    c->pvals.resize(v0 + size_t(W) * W * W, 0.0);
+    auto box = [&](int dx, int dy, int dz) {
+        return v0 + (size_t(dz + rbox) * W + size_t(dy + rbox)) * W + size_t(dx + rbox);
+    };
+    double ss = 0.0;  // sum of squares, in the order of the scan
     for (int dy = -r; dy <= r + 1; ++dy) {
         for (int dx = -r; dx <= r + 1; ++dx) {
             int first = 0, count = 0;
@@ -129,7 +146,9 @@ int build_atom_table(sq_ctx *c, const double *R, double sig, double rc, double g
                         return fail(SQ_EINVAL, "projector sphere column is not contiguous");
                     if (count == 0) first = dz;
                     ++count;
-                    c->pvals.push_back(std::exp(-r2 / (2.0 * sig * sig)));
+                    const double v = std::exp(-r2 / (2.0 * sig * sig));
+                    c->pvals[box(dx, dy, dz)] = v;
+                    ss += v * v;
                 }
             }
             if (count == 0) continue;
@@ -139,7 +158,7 @@ int build_atom_table(sq_ctx *c, const double *R, double sig, double rc, double g
             run.dy = int8_t(dy);
             run.dz0 = int8_t(first);
             run.len = uint8_t(count);
-            run.vstart = int32_t(c->pvals.size() - count);
+            run.vstart = int32_t(box(dx, dy, first));
             c->runs.push_back(run);
             const int lo[3] = {dx, dy, first}, hi[3] = {dx, dy, first + count - 1};
             for (int k = 0; k < 3; ++k) {
@@ -152,15 +171,12 @@ int build_atom_table(sq_ctx *c, const double *R, double sig, double rc, double g
     if (at.nrun == 0) {
         for (int k = 0; k < 3; ++k) at.dmin[k] = at.dmax[k] = 0;
     }
-    // normalise on the grid: h^3 sum chi^2 = 1 over the whole sphere
-    double ss = 0.0;
-    for (size_t i = v0; i < c->pvals.size(); ++i) ss += c->pvals[i] * c->pvals[i];
+    // normalise on the grid: h^3 sum chi^2 = 1 over the whole sphere (the
+    // box's zeros stay zero)
     const double norm = std::sqrt(h * h * h * ss);
     for (size_t i = v0; i < c->pvals.size(); ++i) c->pvals[i] /= norm;
     at.coef = gamma * h * h * h;
     c->atoms.push_back(at);
-    if (c->pvals.size() > size_t(std::numeric_limits<int32_t>::max() / 2))
-        return fail(SQ_EINVAL, "projector tables too large");
     return SQ_OK;
 }
 
@@ -202,6 +218,7 @@ sq::RecurrenceArgs recurrence_args(sq_ctx *c) {
     a.runs = c->at<sq::RunDev>(c->off_runs);
     a.pvals = c->at<double>(c->off_pvals);
     a.pvals_bytes = (long long)(c->pvals.size() * sizeof(double));
+    a.pstride = c->pstride;
     a.chi = c->at<double>(c->off_chi);
     a.zeta = c->at<double>(c->off_zeta);
     a.npl = c->npl;
@@ -810,6 +827,13 @@ int sq_setup(sq_ctx **ctx, double cell, double h, int fd_order, double rcut, int
             return fail(SQ_EINVAL, "grid too large: N_d * 8 bytes must stay below 2 GiB");
         laplacian_weights(c->no, c->h, c->w);
 
+        // one box size for every atom's projector values
+        int rbox = 0;
+        for (int a = 0; a < natom; ++a) {
+            const double rc = kb[3 * a + 1];
+            if (is_finite(rc) && rc > 0 && rc / c->h <= 100) rbox = std::max(rbox, sphere_reach(rc, c->h));
+        }
+        c->pstride = (2 * rbox + 2) * (2 * rbox + 2);
         for (int a = 0; a < natom; ++a) {
             const double *R = atom_xyz + 3 * a;
             const double sig = kb[3 * a], rc = kb[3 * a + 1], gam = kb[3 * a + 2];
@@ -820,7 +844,7 @@ int sq_setup(sq_ctx **ctx, double cell, double h, int fd_order, double rcut, int
             if (rc / c->h > 100) return fail(SQ_EINVAL, "projector cut radius exceeds 100 mesh intervals");
             if (std::fabs(R[0]) / c->h > 1e8 || std::fabs(R[1]) / c->h > 1e8 || std::fabs(R[2]) / c->h > 1e8)
                 return fail(SQ_EINVAL, "atom position too far from the cell");
-            int rc2 = build_atom_table(c.get(), R, sig, rc, gam);
+            int rc2 = build_atom_table(c.get(), R, sig, rc, gam, rbox);
             if (rc2) return rc2;
         }
         // deepest overlap of projector spheres at a grid point (periodic count of

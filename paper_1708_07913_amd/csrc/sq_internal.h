@@ -51,7 +51,8 @@ struct AtomDev {
 struct RunDev {
     int8_t dx, dy, dz0;
     uint8_t len;
-    int32_t vstart;  // index of the dz0 value in the flat value array
+    int32_t vstart;  // index of the dz0 value in the flat value array (values of the
+                     // run's later planes follow at strides of RecurrenceArgs::pstride)
 };
 
 enum Flags : int {
@@ -71,8 +72,9 @@ struct RecurrenceArgs {
     int natom;
     const AtomDev *atoms;
     const RunDev *runs;
-    const double *pvals;
+    const double *pvals;    // per-atom boxes of projector values, x fastest
     long long pvals_bytes;
+    int pstride;            // doubles from a projector value to the one a plane above
     double *chi, *zeta;     // per node
     double *lmin, *lmax;    // Lanczos outputs (may be null)
     double *moments;        // N_d x (npl + 1)

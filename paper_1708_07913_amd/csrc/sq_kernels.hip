@@ -125,6 +125,7 @@ struct Lds {
     int ni;
     int bad;
     int nch;  // chains needed by this region (max sphere overlap depth, >= 1)
+    int ps;   // plane stride of the projector value boxes (doubles)
     int item; // work-queue index taken by the workgroup
 };
 
@@ -296,6 +297,7 @@ __device__ void setup_region(const AT &A, Lds<C, T, NCH> &L, int qi, int qj, int
         L.ni = 0;
         L.bad = 0;
         L.nch = 1;
+        L.ps = A.pstride;
         L.runs[S::MAXRUNS] = make_uint2(kSentinelX, 0u);
     }
     for (int i = tid; i < S::NBUF * S::PLANE; i += S::BLOCK) (&L.plane[0][0])[i] = T(0);
@@ -362,7 +364,7 @@ __device__ void setup_region(const AT &A, Lds<C, T, NCH> &L, int qi, int qj, int
             const int pos = atomicAdd(&L.col_fill[col], 1);
             if (pass == 1 && pos < S::MAXRUNS) {
                 L.runs[pos] = make_uint2((unsigned)I | ((unsigned)zl << 8) | ((unsigned)zh << 16),
-                                         (unsigned)(r.vstart - z0));
+                                         (unsigned)(r.vstart - z0 * A.pstride));
             }
         }
         __syncthreads();
@@ -459,7 +461,8 @@ __device__ void setup_region(const AT &A, Lds<C, T, NCH> &L, int qi, int qj, int
 struct Chain {
     int i, e;       // current record, end of the chain
     unsigned rx;    // slot | z_first << 8 | z_last << 16 of the current record
-    int vb;         // value base of the current record
+    int vb;         // value base of the current record (value at plane z: vb + z * ps)
+    int ps;         // plane stride of the value boxes (workgroup-uniform)
     double acc;
     double pv;      // projector value at the plane being processed (fetched one plane ahead)
 
@@ -471,9 +474,10 @@ struct Chain {
         rx = r.x;
         vb = (int)r.y;
     }
-    __device__ __forceinline__ void start(const uint2 *runs, int b, int end, int sentinel) {
+    __device__ __forceinline__ void start(const uint2 *runs, int b, int end, int sentinel, int stride) {
         i = b;
         e = end;
+        ps = stride;
         acc = 0.0;
         load(runs, sentinel);
     }
@@ -481,7 +485,7 @@ struct Chain {
     // run); it is consumed one plane later, so its latency overlaps a plane
     __device__ __forceinline__ void fetch(__amdgpu_buffer_rsrc_t pvr, int z) {
         const bool act = (z >= z0()) & (z <= z1());
-        pv = bload<double>(pvr, act ? (unsigned)(vb + z) * 8u : kIdleOffset, 0u);
+        pv = bload<double>(pvr, act ? (unsigned)(vb + z * ps) * 8u : kIdleOffset, 0u);
     }
     // after plane z: a finished run adds its dot product into s[slot]
     __device__ __forceinline__ void finish(double *s, int z, const uint2 *runs, int sentinel) {
@@ -502,15 +506,17 @@ struct Chain2 {
     int i, e;
     unsigned rx, nrx;  // current and next record: slot | z_first << 8 | z_last << 16
     int vb, nvb;       // their value bases
+    int ps;            // plane stride of the value boxes (workgroup-uniform)
     double acc;
     double pv[2];      // values of planes z and z + 1 (indexed by plane parity)
     double c;          // per-image coefficient of the current record (second Lanczos pass)
 
     __device__ __forceinline__ int sl() const { return (int)(rx & 0xFFu); }
     __device__ __forceinline__ int z1() const { return (int)((rx >> 16) & 0xFFu); }
-    __device__ __forceinline__ void start(const uint2 *runs, int b, int end, int sentinel) {
+    __device__ __forceinline__ void start(const uint2 *runs, int b, int end, int sentinel, int stride) {
         i = b;
         e = end;
+        ps = stride;
         acc = 0.0;
         const uint2 r0 = runs[i < e ? i : sentinel], r1 = runs[i + 1 < e ? i + 1 : sentinel];
         rx = r0.x;
@@ -521,7 +527,8 @@ struct Chain2 {
     __device__ __forceinline__ void fetch(__amdgpu_buffer_rsrc_t pvr, int z) {
         const bool cur = (z >= (int)((rx >> 8) & 0xFFu)) & (z <= (int)((rx >> 16) & 0xFFu));
         const bool nxt = (z >= (int)((nrx >> 8) & 0xFFu)) & (z <= (int)((nrx >> 16) & 0xFFu));
-        const unsigned off = cur ? (unsigned)(vb + z) * 8u : (nxt ? (unsigned)(nvb + z) * 8u : kIdleOffset);
+        const unsigned off =
+            cur ? (unsigned)(vb + z * ps) * 8u : (nxt ? (unsigned)(nvb + z * ps) * 8u : kIdleOffset);
         pv[z & 1] = bload<double>(pvr, off, 0u);
     }
     __device__ __forceinline__ void finish(double *s, int z, const uint2 *runs, int sentinel) {
@@ -577,6 +584,7 @@ template <int C, typename T, int NCH>
 __device__ __forceinline__ void chains_start(const Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr, int column,
                                              Chain (&ch)[NCH], int nch) {
     constexpr int SENT = Shape<C>::MAXRUNS;
+    const int ps = __builtin_amdgcn_readfirstlane(L.ps);
     const bool ok = column >= 0;
     const int b = ok ? L.col_start[column] : 0;
     const int e = ok ? L.col_start[column + 1] : 0;
@@ -584,7 +592,7 @@ __device__ __forceinline__ void chains_start(const Lds<C, T, NCH> &L, __amdgpu_b
     for (int ci = 0; ci < NCH; ++ci) {
         const int s0 = b + (ok ? L.col_off[column][ci] : 0);
         const int s1 = ci + 1 < NCH ? b + (ok ? L.col_off[column][ci + 1] : 0) : e;
-        ch[ci].start(L.runs, s0, s1, SENT);
+        ch[ci].start(L.runs, s0, s1, SENT, ps);
         ch[ci].pv = 0.0;
         if (ci == 0 || ci < nch) ch[ci].fetch(pvr, 0);
     }
@@ -594,6 +602,7 @@ template <int C, typename T, int NCH>
 __device__ __forceinline__ void chains2_start(const Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr, int column,
                                               Chain2 (&ch)[NCH], int nch) {
     constexpr int SENT = Shape<C>::MAXRUNS;
+    const int ps = __builtin_amdgcn_readfirstlane(L.ps);
     const bool ok = column >= 0;
     const int b = ok ? L.col_start[column] : 0;
     const int e = ok ? L.col_start[column + 1] : 0;
@@ -601,7 +610,7 @@ __device__ __forceinline__ void chains2_start(const Lds<C, T, NCH> &L, __amdgpu_
     for (int ci = 0; ci < NCH; ++ci) {
         const int s0 = b + (ok ? L.col_off[column][ci] : 0);
         const int s1 = ci + 1 < NCH ? b + (ok ? L.col_off[column][ci + 1] : 0) : e;
-        ch[ci].start(L.runs, s0, s1, SENT);
+        ch[ci].start(L.runs, s0, s1, SENT, ps);
         ch[ci].pv[0] = ch[ci].pv[1] = 0.0;
         if (ci == 0 || ci < nch) {
             ch[ci].fetch(pvr, 0);
@@ -1408,7 +1417,8 @@ template <bool UP>
 struct ChainD {
     int i, b, e;    // current record, chain range [b, e)
     unsigned rx;    // slot | z_first << 8 | z_last << 16
-    int vb;         // value base of the current record
+    int vb;         // value base of the current record (value at plane z: vb + z * ps)
+    int ps;         // plane stride of the value boxes (workgroup-uniform)
     double acc;
     double pv;      // projector value at the plane being processed
 
@@ -1421,9 +1431,10 @@ struct ChainD {
         rx = r.x;
         vb = (int)r.y;
     }
-    __device__ __forceinline__ void start(const uint2 *runs, int b0, int e0, int sentinel) {
+    __device__ __forceinline__ void start(const uint2 *runs, int b0, int e0, int sentinel, int stride) {
         b = b0;
         e = e0;
+        ps = stride;
         i = UP ? b0 : e0 - 1;
         acc = 0.0;
         pv = 0.0;
@@ -1431,7 +1442,7 @@ struct ChainD {
     }
     __device__ __forceinline__ void fetch(__amdgpu_buffer_rsrc_t pvr, int z) {
         const bool act = (z >= z0()) & (z <= z1());
-        pv = bload<double>(pvr, act ? (unsigned)(vb + z) * 8u : kIdleOffset, 0u);
+        pv = bload<double>(pvr, act ? (unsigned)(vb + z * ps) * 8u : kIdleOffset, 0u);
     }
     // after plane z: a run that ends here adds its dot product into s[slot]
     __device__ __forceinline__ void finish(double *s, int z, const uint2 *runs, int sentinel) {
@@ -1448,6 +1459,7 @@ template <bool UP, int C, typename T, int NCH>
 __device__ __forceinline__ void chainsd_start(const Lds<C, T, NCH> &L, __amdgpu_buffer_rsrc_t pvr, int column,
                                               ChainD<UP> (&ch)[NCH], int nch) {
     constexpr int SENT = Shape<C>::MAXRUNS;
+    const int ps = __builtin_amdgcn_readfirstlane(L.ps);
     const bool ok = column >= 0;
     const int b = ok ? L.col_start[column] : 0;
     const int e = ok ? L.col_start[column + 1] : 0;
@@ -1455,7 +1467,7 @@ __device__ __forceinline__ void chainsd_start(const Lds<C, T, NCH> &L, __amdgpu_
     for (int ci = 0; ci < NCH; ++ci) {
         const int s0 = b + (ok ? L.col_off[column][ci] : 0);
         const int s1 = ci + 1 < NCH ? b + (ok ? L.col_off[column][ci + 1] : 0) : e;
-        ch[ci].start(L.runs, s0, s1, SENT);
+        ch[ci].start(L.runs, s0, s1, SENT, ps);
         if (ci == 0 || ci < nch) ch[ci].fetch(pvr, UP ? 0 : C - 1);
     }
 }
