@@ -218,6 +218,7 @@ def run_ensemble(args):
         mu, e = b.step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    log(f"ensemble: {args.steps} timed pass(es), {wall / args.steps:.2f} s per pass")
     # SCF-style passes that reuse the bounds of the previous pass
     br = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=True, bounds_every=1000)
     br.step()
@@ -227,6 +228,7 @@ def run_ensemble(args):
     torch.cuda.synchronize()
     reuse_s = time.perf_counter() - t1
     del br
+    log(f"ensemble: pass reusing bounds {reuse_s:.2f} s")
     # the same pass with the default tiles (32 nodes per item, occupancy-limited
     # workgroups per CU), for the autotuner's gain
     bd = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=True)
@@ -238,6 +240,7 @@ def run_ensemble(args):
     default_s = time.perf_counter() - t1
     default_tiles = bd.tiles()
     del bd
+    log(f"ensemble: default tiles {default_tiles}: {default_s:.2f} s per pass")
     node_steps = sum(g.nd * (wl.npl // 2) for g, wl in zip(snaps, wls))
     nodes = sum(g.nd for g in snaps)
     rec = {"metric": METRIC, "value": node_steps / (wall / args.steps), "unit": "grid-pt*Chebyshev-steps/s",
