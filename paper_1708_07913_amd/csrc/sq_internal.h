@@ -26,15 +26,15 @@ constexpr int rows_per_thread(int C) { return C > kResidentCube ? 3 : (C >= 29 ?
 constexpr int row_group_threads(int C) { return (C == 29 || C == 31) ? 32 : C; }
 // Doubles per plane of a workgroup's recurrence slot.  The Lanczos ring
 // kernel (cubes up to kResidentCube) stores plane z of a vector thread by
-// thread, element z * slot_plane + t * rows + r for row r of thread t, so that
-// a thread moves all its rows with one 8- or 16-byte access.  The moments
-// kernels and the streamed kernels store the cube's plane, element
+// thread: the thread at x in row group g keeps its rows r at elements
+// z * slot_plane + (g * C + x) * rows + r, so that it moves all its rows with
+// one 8- or 16-byte access and a row group's stores are contiguous.  The
+// moments kernels and the streamed kernels store the cube's plane, element
 // z * C^2 + y * C + x, which fits as slot_plane >= C^2.
 constexpr long long slot_plane(int C) {
     return C > kResidentCube
                ? (long long)C * C
-               : (long long)row_group_threads(C) * ((C + rows_per_thread(C) - 1) / rows_per_thread(C)) *
-                     rows_per_thread(C);
+               : (long long)((C + rows_per_thread(C) - 1) / rows_per_thread(C)) * C * rows_per_thread(C);
 }
 constexpr long long slot_elems_for(int C) { return (long long)C * slot_plane(C); }
 

@@ -561,7 +561,7 @@ struct Cols {
         y0 = t_active ? (tid / S::XW) * RB : 0;
         // lanes past the cube's x range read (and discard) the next padded row
         corner = t_active ? y0 * S::P + x : S::IDLE_CORNER;
-        slot = (t_active && x < C && y0 < C) ? (unsigned)(tid * RB) * 8u : kIdleOffset;
+        slot = (t_active && x < C && y0 < C) ? (unsigned)(((tid / S::XW) * C + x) * RB) * 8u : kIdleOffset;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const bool ok = t_active && (x < C) && (y0 + r < C);
