@@ -68,6 +68,7 @@ def _load():
     lib.sqo_fermi_level.argtypes = [P, ct.c_long, dp, dp, dp, ct.c_double, ct.c_double,
                                     ct.c_double, ct.c_int, dp, ip]
     lib.sqo_density_energy.argtypes = [P, ct.c_long, dp, dp, dp, ct.c_double, dp, dp]
+    lib.sqo_nl_forces.argtypes = [P, lp, ct.c_long, dp, dp, ct.c_double, dp]
     lib.sqo_num_threads.restype = ct.c_int
     _lib = lib
     return lib
@@ -239,3 +240,17 @@ class Oracle:
         _load().sqo_density_energy(self._p, lmin.size, _dp(lmin), _dp(lmax), _dp(mom), float(mu),
                                    _dp(rho), _dp(out))
         return rho, out
+
+    def nl_forces(self, lmin, lmax, mu, nodes=None) -> np.ndarray:
+        """Nonlocal atomic forces (natom x 3, Ha/Bohr) from the given nodes
+        (all by default; lmin/lmax per listed node), Sec. 3.4."""
+        arr, cnt = self._nodes(nodes)
+        lmin = _f64(lmin)
+        lmax = _f64(lmax)
+        assert lmin.size == cnt and lmax.size == cnt
+        f = np.zeros((self._atoms.shape[0], 3))
+        lp = arr.ctypes.data_as(ct.POINTER(ct.c_long)) if arr is not None else None
+        rc = _load().sqo_nl_forces(self._p, lp, cnt, _dp(lmin), _dp(lmax), float(mu), _dp(f))
+        if rc != 0:
+            raise RuntimeError(f"sqo_nl_forces failed ({rc})")
+        return f

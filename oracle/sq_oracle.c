@@ -15,6 +15,7 @@
  *   Lanczos spectral bounds, Chebyshev recurrence, moments,
  *   product property, coefficients, Fermi level (Brent), density      -- Sec. 3.2
  *   band-structure and entropy energies                               -- Sec. 3.3
+ *   nonlocal atomic forces (recurrence to n_pl, FD gradient)         -- Sec. 3.4, 3.1
  *
  * Readings of points the paper leaves open (all listed in the design notes):
  *   - mesh refit h = L / round(L/h); cube half-width m = floor(R_cut/h + 1/2);
@@ -252,6 +253,7 @@ typedef struct {
     long *idx;
     double *p;
     double coef;             /* gamma * h^3 */
+    int atom;                /* the atom this image belongs to */
 } sqo_image;
 
 typedef struct {
@@ -312,6 +314,7 @@ static int region_build(const sqo *S, long q, sqo_region *R)
             sqo_image im;
             im.count = A->count;
             im.coef = A->gamma * h3;
+            im.atom = a;
             im.idx = (long *)malloc(sizeof(long) * (A->count > 0 ? A->count : 1));
             im.p = (double *)malloc(sizeof(double) * (A->count > 0 ? A->count : 1));
             for (int e = 0; e < A->count; e++) {
@@ -354,6 +357,7 @@ static int region_build(const sqo *S, long q, sqo_region *R)
                     sqo_image im;
                     im.count = cnt;
                     im.coef = A->gamma * h3;
+                    im.atom = a;
                     im.idx = (long *)malloc(sizeof(long) * cnt);
                     im.p = (double *)malloc(sizeof(double) * cnt);
                     cnt = 0;
@@ -811,6 +815,130 @@ int sqo_density_energy(const sqo *S, long count, const double *lmin, const doubl
     free(eb);
     free(en);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Nonlocal atomic forces (Sec. 3.4, nonlocal component).                    */
+/*   f_I = -4 sum_{I' images of I} sum_q w_q^T V_q^{I'} grad_{h,q} u_q,       */
+/*   u_q = sum_{j=0}^{n_pl} c_q^j t_q^j  (the recurrence run to n_pl),        */
+/* with V^{I'} = gamma h^3 p p^T, so w_q^T V^{I'} = gamma h^3 p(q) p^T, and   */
+/* grad_{h,q} the central-difference gradient of Sec. 3.1 restricted to the  */
+/* region of influence (legs leaving the cube dropped; periodic in the       */
+/* whole-cell mode).  Only nodes inside some projector sphere contribute.    */
+/* ------------------------------------------------------------------------ */
+static void fd_gradient_weights(int no, double h, double *wt)
+{
+    double f2 = factorial(no) * factorial(no);
+    wt[0] = 0.0;
+    for (int d = 1; d <= no; d++)
+        wt[d] = ((d % 2) ? 1.0 : -1.0) / (h * d) * f2 / (factorial(no - d) * factorial(no + d));
+}
+
+/* (grad_{h,q} u)(l) along axis ax for local point l of the region. */
+static double grad_at(const sqo *S, const double *wt, const double *u, long l, int ax)
+{
+    double g = 0.0;
+    if (S->region == SQO_GAMMA) {
+        long n = S->n, i = l % n, j = (l / n) % n, k = l / (n * n);
+        for (int d = 1; d <= S->no; d++) {
+            long ip = i, jp = j, kp = k, im = i, jm = j, km = k;
+            if (ax == 0) { ip = imod(i + d, n); im = imod(i - d, n); }
+            if (ax == 1) { jp = imod(j + d, n); jm = imod(j - d, n); }
+            if (ax == 2) { kp = imod(k + d, n); km = imod(k - d, n); }
+            g += wt[d] * (u[ip + n * (jp + n * kp)] - u[im + n * (jm + n * km)]);
+        }
+        return g;
+    }
+    long C = S->C, a = l % C, b = (l / C) % C, c = l / (C * C);
+    long pos = ax == 0 ? a : (ax == 1 ? b : c);
+    long stride = ax == 0 ? 1 : (ax == 1 ? C : C * C);
+    for (int d = 1; d <= S->no; d++) {
+        if (pos + d < C) g += wt[d] * u[l + d * stride];
+        if (pos - d >= 0) g -= wt[d] * u[l - d * stride];
+    }
+    return g;
+}
+
+#define SQO_MAX_CENTRE_IMAGES 16
+
+int sqo_nl_forces(const sqo *S, const long *nodes, long count, const double *lmin, const double *lmax,
+                  double mu, double *forces)
+{
+    int npl = S->npl;
+    int err = 0;
+    double wt[8];
+    fd_gradient_weights(S->no, S->h, wt);
+    /* per node: up to SQO_MAX_CENTRE_IMAGES (atom, force) contributions, summed
+       afterwards in node order */
+    int *atom = (int *)malloc(sizeof(int) * SQO_MAX_CENTRE_IMAGES * (count > 0 ? count : 1));
+    double *fc = (double *)malloc(sizeof(double) * 3 * SQO_MAX_CENTRE_IMAGES * (count > 0 ? count : 1));
+    if (!atom || !fc) { free(atom); free(fc); return -2; }
+    for (long t = 0; t < SQO_MAX_CENTRE_IMAGES * count; t++) atom[t] = -1;
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * 5 * S->ns);
+        double *c = (double *)malloc(sizeof(double) * (npl + 1));
+#pragma omp for schedule(dynamic, 4)
+        for (long t = 0; t < count; t++) {
+            long q = nodes ? nodes[t] : t;
+            sqo_region R;
+            if (!buf || !c || region_build(S, q, &R) != 0) {
+#pragma omp atomic write
+                err = -2;
+                continue;
+            }
+            long lc = center_index(S, q);
+            /* images whose sphere contains the node, with p(q) */
+            int ci[SQO_MAX_CENTRE_IMAGES];
+            double pc[SQO_MAX_CENTRE_IMAGES];
+            int nc = 0;
+            for (int I = 0; I < R.nimg; I++)
+                for (int e = 0; e < R.img[I].count; e++)
+                    if (R.img[I].idx[e] == lc && nc < SQO_MAX_CENTRE_IMAGES) {
+                        ci[nc] = I;
+                        pc[nc] = R.img[I].p[e];
+                        nc++;
+                    }
+            if (nc == 0) { region_free(&R); continue; }
+            double chi, zeta;
+            scale_bounds(S, lmin[t], lmax[t], &chi, &zeta);
+            sqo_coefficients(S, mu, lmin[t], lmax[t], c, NULL, NULL);
+            double *tm1 = buf, *t0 = buf + S->ns, *tp1 = buf + 2 * S->ns, *hv = buf + 3 * S->ns;
+            double *u = buf + 4 * S->ns;
+            for (long a = 0; a < S->ns; a++) tm1[a] = 0.0;
+            tm1[lc] = 1.0;                               /* t^0 = w_q */
+            apply_hhat(S, &R, chi, zeta, tm1, t0);      /* t^1 = Hhat w_q */
+            for (long a = 0; a < S->ns; a++) u[a] = c[0] * tm1[a] + c[1] * t0[a];
+            for (int k = 1; k < npl; k++) {             /* t^{k+1}, k + 1 = 2 .. n_pl */
+                apply_hhat(S, &R, chi, zeta, t0, hv);
+                for (long a = 0; a < S->ns; a++) tp1[a] = 2.0 * hv[a] - tm1[a];
+                for (long a = 0; a < S->ns; a++) u[a] += c[k + 1] * tp1[a];
+                double *tmp = tm1; tm1 = t0; t0 = tp1; tp1 = tmp;
+            }
+            for (int m = 0; m < nc; m++) {
+                const sqo_image *im = &R.img[ci[m]];
+                double sv[3] = {0.0, 0.0, 0.0};        /* p^T grad_{h,q} u */
+                for (int e = 0; e < im->count; e++)
+                    for (int ax = 0; ax < 3; ax++) sv[ax] += im->p[e] * grad_at(S, wt, u, im->idx[e], ax);
+                atom[t * SQO_MAX_CENTRE_IMAGES + m] = im->atom;
+                for (int ax = 0; ax < 3; ax++)
+                    fc[(t * SQO_MAX_CENTRE_IMAGES + m) * 3 + ax] = -4.0 * im->coef * pc[m] * sv[ax];
+            }
+            region_free(&R);
+        }
+        free(buf);
+        free(c);
+    }
+    for (long a = 0; a < 3L * S->natom; a++) forces[a] = 0.0;
+    for (long t = 0; t < count; t++)
+        for (int m = 0; m < SQO_MAX_CENTRE_IMAGES; m++) {
+            int at = atom[t * SQO_MAX_CENTRE_IMAGES + m];
+            if (at < 0) continue;
+            for (int ax = 0; ax < 3; ax++) forces[3 * at + ax] += fc[(t * SQO_MAX_CENTRE_IMAGES + m) * 3 + ax];
+        }
+    free(atom);
+    free(fc);
+    return err;
 }
 
 int sqo_num_threads(void)

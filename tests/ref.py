@@ -168,3 +168,49 @@ def bloch_hamiltonian(n, h, w, veff, tables, k):
 
 def fermi(x):
     return 0.5 * (1.0 - np.tanh(0.5 * x))
+
+
+def fd_gradient_weights_taylor(no: int) -> list[Fraction]:
+    """Central first-derivative weights of order 2 no for unit spacing, from
+    the moment conditions on an antisymmetric stencil:
+    f'(0) ~ sum_d g_d (f_d - f_-d) with sum_d 2 d^(2p+1) g_d = delta_{p,0},
+    p = 0 .. no - 1, solved exactly.  Returns [0, g_1, ..., g_no]."""
+    A = [[Fraction(2 * d ** (2 * p + 1)) for d in range(1, no + 1)] for p in range(no)]
+    b = [Fraction(1) if p == 0 else Fraction(0) for p in range(no)]
+    for col in range(no):
+        piv = next(r for r in range(col, no) if A[r][col] != 0)
+        A[col], A[piv] = A[piv], A[col]
+        b[col], b[piv] = b[piv], b[col]
+        for r in range(no):
+            if r != col and A[r][col] != 0:
+                f = A[r][col] / A[col][col]
+                A[r] = [x - f * y for x, y in zip(A[r], A[col])]
+                b[r] -= f * b[col]
+    return [Fraction(0)] + [b[i] / A[i][i] for i in range(no)]
+
+
+def periodic_gradient(n, h, g, ax):
+    """Dense periodic FD derivative along axis ax (0 = x, fastest index) of an
+    n^3 grid, weights g = [0, g_1, ..] for unit spacing."""
+    N = n ** 3
+    G = np.zeros((N, N))
+    idx = np.arange(N)
+    coords = [idx % n, (idx // n) % n, idx // (n * n)]
+    for d in range(1, len(g)):
+        for s in (+1, -1):
+            c = [x.copy() for x in coords]
+            c[ax] = (c[ax] + s * d) % n
+            tgt = c[0] + n * (c[1] + n * c[2])
+            np.add.at(G, (idx, tgt), s * float(g[d]) / h)
+    return G
+
+
+def projector_vectors(n, tables):
+    """Each atom's projector as a periodic grid vector (sphere wrapped into the cell)."""
+    out = []
+    for ijk, p, gam in tables:
+        loc = np.mod(ijk, n)
+        v = np.zeros(n ** 3)
+        np.add.at(v, loc[:, 0] + n * (loc[:, 1] + n * loc[:, 2]), p)
+        out.append((v, gam))
+    return out
