@@ -173,6 +173,19 @@ int sq_density_energy(sq_ctx *ctx, const double *moments, double mu, double *rho
 int sq_density_energy_static(sq_ctx *ctx, const double *moments, double mu, double *rho,
                              double *energies, void *stream);
 
+/* Nonlocal atomic forces (Sec. 3.4, nonlocal component, with the FD gradient
+ * of Sec. 3.1): forces (host, natom x 3 FP64, Ha/Bohr, row per atom in the
+ * order of sq_setup's atom_xyz) =
+ *   f_I = -4 sum_{I' images of I} sum_q gamma h^3 p_{I'}(q) p_{I'}^T grad_{h,q} u_q,
+ *   u_q = sum_{j=0}^{n_pl} c_q^j t_q^j,
+ * with the recurrence run to n_pl (twice the density's length) at the
+ * current bounds and the Chebyshev coefficients c_q^j of the Fermi function
+ * at Fermi level mu (from sq_fermi_level).  FP64 in both precision modes.
+ * Requires bounds (SQ_ESTATE otherwise), regions of at most 31 points per
+ * side and n_pl <= 256 (SQ_EINVAL otherwise).  Uses the workspace's vector
+ * buffers; synchronises `stream`. */
+int sq_nl_forces(sq_ctx *ctx, double mu, double *forces, void *stream);
+
 /* Release the host tables (never touches caller-owned device memory). */
 void sq_destroy(sq_ctx *ctx);
 

@@ -64,7 +64,7 @@ struct sq_ctx {
     int pstride = 0;    // doubles between a projector value and the one a plane above
     int max_overlap = 0;
     size_t off_atoms = 0, off_runs = 0, off_pvals = 0, off_chi = 0, off_zeta = 0, off_ctab = 0,
-           off_rk = 0, off_W = 0, off_part = 0, off_scal = 0, off_flags = 0, off_v32 = 0,
+           off_rk = 0, off_W = 0, off_part = 0, off_scal = 0, off_flags = 0, off_v32 = 0, off_forces = 0,
            off_slots = 0, off_wslots = 0, off_xslots = 0, off_args = 0, total = 0;
     sq::RecurrenceArgs args_host[2] = {};  // staged launch arguments (Lanczos, moments)
     char *ws = nullptr;
@@ -104,6 +104,22 @@ void laplacian_weights(int no, double h, double *w) {
 // Reach of an atom's projector sphere in grid steps from its base node: the
 // sphere's points have offsets -r .. r + 1 in each direction.
 int sphere_reach(double rc, double h) { return int(std::ceil(rc / h)) + 1; }
+
+// Central first-derivative weights of order 2 n_o (Sec. 3.1 gradient):
+// gw_d = (-1)^{d+1} / (h d) (n_o!)^2 / ((n_o - d)! (n_o + d)!).
+void gradient_weights(int no, double h, double *gw) {
+    gw[0] = 0.0;
+    for (int d = 1; d <= sq::kNoMax; ++d) {
+        if (d > no) {
+            gw[d] = 0.0;
+            continue;
+        }
+        double ratio = 1.0;
+        for (int i = 1; i <= d; ++i) ratio *= double(no - d + i) / double(no + i);
+        const double sign = (d & 1) ? 1.0 : -1.0;
+        gw[d] = sign * ratio / (h * double(d));
+    }
+}
 
 // Projector of one atom as z-runs over (dx, dy) columns of its sphere.  The
 // values sit in a box of (2 rbox + 2)^3 doubles, x fastest and zero outside
@@ -228,6 +244,10 @@ sq::RecurrenceArgs recurrence_args(sq_ctx *c) {
     a.start_norm = c->start_norm;
     a.margin = c->opt.margin;
     a.bounds_tol = c->opt.precision == SQ_FP32_MIXED ? 1e-5 : 1e-10;
+    gradient_weights(c->no, c->h, a.gw);
+    a.ctab = c->at<double>(c->off_ctab);
+    a.rk = c->at<double>(c->off_rk);
+    a.kT = c->kT;
     return a;
 }
 
@@ -294,6 +314,7 @@ void layout(sq_ctx *c) {
     c->off_part = take(3 * kReduceBlocks * sizeof(double));
     c->off_scal = take(8 * sizeof(double));
     c->off_flags = take(64);
+    c->off_forces = take(c->atoms.size() * 3 * sizeof(double));
     c->off_args = take(2 * sizeof(sq::RecurrenceArgs));
     c->off_v32 = take(c->opt.precision == SQ_FP32_MIXED ? size_t(c->nd) * sizeof(float) : 0);
     // one slot per workgroup: C planes of slot_plane(C) doubles
@@ -1095,6 +1116,37 @@ int sq_density_energy_static(sq_ctx *c, const double *moments, double mu, double
         energies[2] = v[0] + v[1];
         energies[3] = h3 * v[2];
         return SQ_OK;
+    });
+}
+
+int sq_nl_forces(sq_ctx *c, double mu, double *forces, void *stream) {
+    return guarded([&]() -> int {
+        int rc = check_ctx(c, kBounds);
+        if (rc) return rc;
+        if (!forces) return fail(SQ_EINVAL, "forces must be a host array of natom x 3 doubles");
+        if (!is_finite(mu)) return fail(SQ_EINVAL, "mu must be finite");
+        if (c->C > sq::kResidentCube)
+            return fail(SQ_EINVAL, "nonlocal forces need regions of at most 31 points per side");
+        if (c->nq > sq::kMaxForceNq) return fail(SQ_EINVAL, "nonlocal forces need n_pl <= 256");
+        const size_t na = c->atoms.size();
+        for (size_t i = 0; i < 3 * na; ++i) forces[i] = 0.0;
+        if (na == 0) return SQ_OK;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        double *fdev = c->at<double>(c->off_forces);
+        rc = hip_check(sq::launch_zero_doubles(fdev, int(3 * na), s), "clearing forces");
+        if (rc) return rc;
+        sq::RecurrenceArgs a = recurrence_args(c);
+        a.mu = mu;
+        a.forces = fdev;
+        sq::LaunchArgs k;
+        rc = stage_launch(c, a, 1, s, &k);
+        if (rc) return rc;
+        rc = hip_check(sq::launch_forces(k, c->C, c->nch, c->nwg_lanczos, s), "launching forces");
+        if (rc) return rc;
+        rc = hip_check(hipMemcpyAsync(forces, fdev, 3 * na * sizeof(double), hipMemcpyDeviceToHost, s),
+                       "reading forces");
+        if (rc) return rc;
+        return hip_check(hipStreamSynchronize(s), "forces");
     });
 }
 

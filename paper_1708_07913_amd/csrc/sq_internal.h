@@ -85,7 +85,15 @@ struct RecurrenceArgs {
     double start_norm;      // norm of the unnormalised Lanczos start vector
     double margin;
     double bounds_tol;      // allowed |moment| - 1
+    // nonlocal forces (Sec. 3.4)
+    double gw[kNoMax + 1];  // FD gradient weights (zero beyond n_o)
+    const double *ctab;     // (n_pl + 1)^2 coefficient table, [j][k]
+    const double *rk;       // n_pl + 1 Chebyshev-Gauss nodes
+    double mu, kT;          // Fermi level, smearing (Ha)
+    double *forces;         // natom x 3, accumulated
 };
+
+constexpr int kMaxForceNq = 257;  // n_pl + 1 limit of the force kernel
 
 // One unit of a work queue: nodes q0 .. q1 - 1 of snapshot `snap`.
 struct WorkItem {
@@ -259,7 +267,9 @@ struct FermiSnap {
 // C is the cube side and nch the projector chains of every snapshot launched.
 hipError_t launch_lanczos(const LaunchArgs &k, int C, int nch, int nwg, hipStream_t s);
 hipError_t launch_moments(const LaunchArgs &k, int C, int nch, bool mixed, int nwg, hipStream_t s);
+hipError_t launch_forces(const LaunchArgs &k, int C, int nch, int nwg, hipStream_t s);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
+hipError_t launch_zero_doubles(double *p, int n, hipStream_t s);
 int recurrence_block(int C);
 hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int nch, int *blocks_per_cu);
 hipError_t launch_set_bounds(const double *lmin, const double *lmax, double *chi, double *zeta,

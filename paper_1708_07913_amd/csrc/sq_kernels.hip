@@ -1554,9 +1554,13 @@ struct MomentsStep {
     double al, invz, c0;
     int k;
     bool prev;  // t^{k-1} is read from the slot (k > 0)
+    // force mode: u <- ua t^k + u + uc t^{k+1} (ua = c_0 at k = 0, else 0)
+    double ua, uc;
 };
 
-template <int C, int NCH, bool UP, typename AT>
+// FORCE: instead of the moments, accumulate u = sum_j c_j t^j in the vector
+// buffer `ur` (same layout as the slot; read and rewritten plane by plane).
+template <int C, int NCH, bool UP, bool FORCE = false, typename AT>
 __device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, NCH> &L, const Cols<C> &cl,
                                                    double (&R)[Shape<C>::RB][C + NO + 1],
                                                    __amdgpu_buffer_rsrc_t slr, __amdgpu_buffer_rsrc_t vr,
@@ -1564,7 +1568,7 @@ __device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, N
                                                    const unsigned (&voff)[Shape<C>::RB], unsigned zbase,
                                                    const double (&kw)[NO + 1], const MomentsStep &st,
                                                    double *snext, int nch, int centre_r, double *mrow,
-                                                   double &d1, double &d2) {
+                                                   double &d1, double &d2, __amdgpu_buffer_rsrc_t ur) {
     using S = Shape<C>;
     using D = RingDir<UP>;
     constexpr int RB = S::RB;
@@ -1584,7 +1588,11 @@ __device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, N
     unsigned poff[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) poff[r] = st.prev ? voff[r] : kIdleOffset;
-    double vzq[PPB][RB], tpn[TPA][RB];
+    double vzq[PPB][RB], tpn[TPA][RB], upn[FORCE ? TPA : 1][RB];
+    // u starts at zero: at k = 0 its loads use the idle offset
+    unsigned uoff[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) uoff[r] = st.prev ? voff[r] : kIdleOffset;
     auto vload = [&](int i, int r) {
         const int zz = D::plane(i, C);
         return bload<double>(vr, vcol[r], (unsigned)(n * n) * ((zb + (unsigned)zz) % (unsigned)n) * 8u);
@@ -1596,11 +1604,16 @@ __device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, N
 #pragma unroll
         for (int a = 0; a < TPA; ++a)
             tpn[a][r] = a < C ? bload<double>(slr, poff[r], (unsigned)(D::plane(a, C) * S::CC) * 8u) : 0.0;
+        if constexpr (FORCE) {
+#pragma unroll
+            for (int a = 0; a < TPA; ++a)
+                upn[a][r] = a < C ? bload<double>(ur, uoff[r], (unsigned)(D::plane(a, C) * S::CC) * 8u) : 0.0;
+        }
     }
 #pragma unroll
     for (int g = 0; g < C; g += PPB) {
         const int pb = PPB * ((g / PPB) & 1);
-        double vz[PPB][RB], tprev[PPB][RB];
+        double vz[PPB][RB], tprev[PPB][RB], uprev[PPB][RB];
 #pragma unroll
         for (int h = 0; h < PPB; ++h) {
             const int i = g + h;
@@ -1613,6 +1626,12 @@ __device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, N
                     if (i + PPB < C) vzq[i % PPB][r] = vload(i + PPB, r);
                     if (i + TPA < C)
                         tpn[i % TPA][r] = bload<double>(slr, poff[r], (unsigned)(D::plane(i + TPA, C) * S::CC) * 8u);
+                    if constexpr (FORCE) {
+                        uprev[h][r] = upn[i % TPA][r];
+                        if (i + TPA < C)
+                            upn[i % TPA][r] =
+                                bload<double>(ur, uoff[r], (unsigned)(D::plane(i + TPA, C) * S::CC) * 8u);
+                    }
                     L.plane[pb + h][cl.pcw[r]] = R[r][z + D::IN];
                 }
             }
@@ -1645,6 +1664,7 @@ __device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, N
                     if (!cl.valid(r)) nvd = 0.0;
                     R[r][z + D::OUT] = nvd;
                     bstore(tz, slr, voff[r], sz);  // t^k over t^{k-1}
+                    if constexpr (FORCE) bstore(st.ua * tz + uprev[h][r] + st.uc * nvd, ur, voff[r], sz);
                     d1 += nvd * nvd;
                     d2 += nvd * tz;
                     pin(d1);
@@ -1657,7 +1677,7 @@ __device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, N
                         }
                     }
                     chainsd_advance<UP, C, NCH>(ch[r], snext, L.runs, pvr, z, nch);
-                    if (z == MC && centre_r == r) {
+                    if (!FORCE && z == MC && centre_r == r) {
                         mrow[st.k + 1] = nvd;
                         if (st.k == 0) L.bc[2] = nvd;
                         if (fabs(nvd) > 1.0 + A.bounds_tol) atomicOr(A.flags, kFlagBounds);
@@ -1752,7 +1772,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_ring_kernel(LaunchArg
             st.prev = k > 0;
             double d[2] = {0.0, 0.0};
             moments_ring_sweep<C, NCH, UP>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st, L.s[cur ^ 1], nch,
-                                           centre_r, mrow, d[0], d[1]);
+                                           centre_r, mrow, d[0], d[1], slr);
             // the sweep ended on a barrier: the dots of t^{k+1} are complete.
             // Coefficients of the next step, and its dot accumulator cleared;
             // the reduction's barrier publishes both.
@@ -1778,6 +1798,200 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_ring_kernel(LaunchArg
             step(k, std::true_type());
             step(k + 1, std::false_type());
         }
+    }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Nonlocal atomic forces (Sec. 3.4, nonlocal component), FP64, resident cubes:
+//   f_I = -4 sum_{I' images of I} sum_q gamma h^3 p_{I'}(q) p_{I'}^T grad_{h,q} u_q,
+//   u_q = sum_{j=0}^{n_pl} c_q^j t_q^j,
+// for the nodes q inside some projector sphere (the other nodes add nothing).
+// The recurrence runs to n_pl on the register ring with u accumulated in the
+// workgroup's second buffer; then every point x of a centre image's sphere in
+// the cube adds p(x) (grad_{h,q} u)(x), the gradient being the Sec. 3.1 central
+// difference with legs that leave the cube dropped.
+// ---------------------------------------------------------------------------
+struct ForcesLds {
+    double gk[kMaxForceNq];  // Fermi function at the quadrature nodes
+    double cj[kMaxForceNq];  // c_q^j
+    double fs[4][3];         // p^T grad u of the centre images
+    double pc[4];            // p_I(q)
+    int img[4];              // centre images (region slots)
+    int nc;
+};
+
+template <int C, int NCH>
+__global__ __launch_bounds__(Shape<C>::BLOCK) void forces_ring_kernel(LaunchArgs K) {
+    using S = Shape<C>;
+    constexpr int RB = S::RB;
+    constexpr int MC = (C - 1) / 2;
+    constexpr int NR = C + NO + 1;
+    static_assert(!S::STREAM, "register ring: resident cubes only");
+    __shared__ Lds<C, double, NCH> L;
+    __shared__ ForcesLds FL;
+    const int tid = threadIdx.x;
+    Cols<C> cl;
+    cl.init(tid);
+    int centre_r = -1;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (cl.col[r] == MC * C + MC) centre_r = r;
+    const long long slot_bytes = K.slot_elems * 8;
+    double *ubuf = reinterpret_cast<double *>(K.wslots) + (long long)blockIdx.x * K.slot_elems;
+    const __amdgpu_buffer_rsrc_t slr =
+        make_rsrc(reinterpret_cast<double *>(K.slots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
+    const __amdgpu_buffer_rsrc_t ulr = make_rsrc(ubuf, slot_bytes);
+    unsigned voff[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * 8u : kIdleOffset;
+
+    WorkSource work;
+    SnapPtr Ap;
+    long long qfirst, qend, qstep;
+    while (work.next(K, L, tid, Ap, qfirst, qend, qstep)) {
+    const auto &A = *Ap;
+    const int n = A.n;
+    const int npl = A.npl, nq = npl + 1;
+    const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
+    const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
+    const double kin0 = -3.0 * A.w[0];
+
+    for (long long q = qfirst; q < qend; q += qstep) {
+        int qi, qj, qk;
+        node_coords(q, n, qi, qj, qk);
+        setup_region(A, L, qi, qj, qk, tid);
+        // images whose sphere contains the node: the centre column's runs
+        // that cover the centre plane
+        if (tid == 0) {
+            constexpr int cc = MC * C + MC;
+            int nc = 0;
+            for (int i = L.col_start[cc]; i < L.col_start[cc + 1] && i < S::MAXRUNS; ++i) {
+                const uint2 rr = L.runs[i];
+                const int z0 = (int)((rr.x >> 8) & 0xFFu), z1 = (int)((rr.x >> 16) & 0xFFu);
+                if (z0 <= MC && MC <= z1 && nc < 4) {
+                    FL.img[nc] = (int)(rr.x & 0xFFu);
+                    FL.pc[nc] = A.pvals[(int)rr.y + MC * A.pstride];
+                    ++nc;
+                }
+            }
+            FL.nc = nc;
+            for (int i = 0; i < 12; ++i) (&FL.fs[0][0])[i] = 0.0;
+        }
+        __syncthreads();
+        const int ncent = FL.nc;
+        if (ncent == 0) continue;
+        const int ni = L.ni < kMaxImages ? L.ni : kMaxImages;
+        const int nch = L.nch;
+        const unsigned zbase = (unsigned)pmod(qk - A.m, n);
+        const double chi = uniform(A.chi[q]), zeta = uniform(A.zeta[q]);
+        const double invz = uniform(1.0 / zeta);
+        // c_q^j by discrete orthogonality (Sec. 3.2), j = 0 .. n_pl
+        for (int k = tid; k < nq; k += S::BLOCK)
+            FL.gk[k] = 1.0 / (1.0 + exp((zeta * A.rk[k] + chi - A.mu) / A.kT));
+        __syncthreads();
+        for (int j = tid; j < nq; j += S::BLOCK) {
+            double c = 0.0;
+            for (int k = 0; k < nq; ++k) c += A.ctab[j * nq + k] * FL.gk[k];
+            FL.cj[j] = c;
+        }
+        double kw[NO + 1];
+        kw[0] = 0.0;
+#pragma unroll
+        for (int d = 1; d <= NO; ++d) kw[d] = uniform(-0.5 * A.w[d] * invz);
+        unsigned vcol[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            vcol[r] = cl.valid(r) ? (unsigned)(pmod(qi - A.m + cl.x, n) + n * pmod(qj - A.m + cl.y0 + r, n)) * 8u
+                                  : kIdleOffset;
+        // t^0 = e_q in the upward sweep's input layout
+        double R[RB][NR];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const int z = i - (NO + 1);
+                R[r][i] = (z >= 0 && centre_r == r && z == MC) ? 1.0 : 0.0;
+            }
+        int cur = 0;
+        projector_dots<false>(L, pvr, cl, cur, nch, [&](int r, int z) {
+            return (centre_r == r && z == MC) ? 1.0 : 0.0;
+        });
+        MomentsStep st;
+        st.invz = invz;
+        st.c0 = uniform(kin0 - chi);
+        for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK)
+            L.cs[i] = i < ni ? invz * L.img_coef[i] * L.s[cur][i] : 0.0;
+        __syncthreads();
+        auto step = [&](int k, auto up) {
+            constexpr bool UP = decltype(up)::value;
+            st.al = k == 0 ? 1.0 : 2.0;
+            st.k = k;
+            st.prev = k > 0;
+            st.ua = uniform(k == 0 ? FL.cj[0] : 0.0);
+            st.uc = uniform(FL.cj[k + 1]);
+            double d[2] = {0.0, 0.0};
+            moments_ring_sweep<C, NCH, UP, true>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st, L.s[cur ^ 1],
+                                                 nch, centre_r, nullptr, d[0], d[1], ulr);
+            const double scale = uniform(2.0 * invz);
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) {
+                L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur ^ 1][i] : 0.0;
+                L.s[cur][i] = 0.0;
+            }
+            __syncthreads();
+            cur ^= 1;
+        };
+        // n_pl steps (t^1 .. t^{n_pl}), an even number
+        for (int k = 0; k < npl; k += 2) {
+            step(k, std::true_type());
+            step(k + 1, std::false_type());
+        }
+        // p^T grad_{h,q} u for the centre images: one run record per thread
+        const int nrec = L.col_start[S::CC] < S::MAXRUNS ? L.col_start[S::CC] : S::MAXRUNS;
+        for (int i = tid; i < nrec; i += S::BLOCK) {
+            const uint2 rr = L.runs[i];
+            const int I = (int)(rr.x & 0xFFu);
+            int m = -1;
+            for (int mm = 0; mm < ncent; ++mm)
+                if (FL.img[mm] == I) m = mm;
+            if (m < 0) continue;
+            int lo = 0, hi = S::CC;  // column: last c with col_start[c] <= i
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (L.col_start[mid] <= i) lo = mid;
+                else hi = mid;
+            }
+            const int x = lo % C, y = lo / C;
+            const int z0 = (int)((rr.x >> 8) & 0xFFu), z1 = (int)((rr.x >> 16) & 0xFFu);
+            double g3[3] = {0.0, 0.0, 0.0};
+            for (int z = z0; z <= z1; ++z) {
+                const double p = A.pvals[(int)rr.y + z * A.pstride];
+                const double *uz = ubuf + (long long)z * S::CC + y * C + x;
+                double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+                for (int d = 1; d <= NO; ++d) {
+                    const double w = A.gw[d];
+                    if (x + d < C) gx += w * uz[d];
+                    if (x - d >= 0) gx -= w * uz[-d];
+                    if (y + d < C) gy += w * uz[d * C];
+                    if (y - d >= 0) gy -= w * uz[-d * C];
+                    if (z + d < C) gz += w * uz[d * S::CC];
+                    if (z - d >= 0) gz -= w * uz[-d * S::CC];
+                }
+                g3[0] += p * gx;
+                g3[1] += p * gy;
+                g3[2] += p * gz;
+            }
+            atomicAdd(&FL.fs[m][0], g3[0]);
+            atomicAdd(&FL.fs[m][1], g3[1]);
+            atomicAdd(&FL.fs[m][2], g3[2]);
+        }
+        __syncthreads();
+        if (tid < 3 * ncent) {
+            const int m = tid / 3, ax = tid % 3, I = FL.img[m];
+            atomicAdd(&A.forces[3 * L.img_atom[I] + ax], -4.0 * L.img_coef[I] * FL.pc[m] * FL.fs[m][ax]);
+        }
+        __syncthreads();
     }
     }
 }
@@ -1997,10 +2211,10 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_mixed_kernel(LaunchAr
                     double d1 = 0.0, d2 = 0.0;
                     if (h == 0)
                         moments_ring_sweep<C, NCH, true>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st,
-                                                         L.s[cur ^ 1], nch, centre_r, mrow, d1, d2);
+                                                         L.s[cur ^ 1], nch, centre_r, mrow, d1, d2, slr);
                     else
                         moments_ring_sweep<C, NCH, false>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st,
-                                                          L.s[cur ^ 1], nch, centre_r, mrow, d1, d2);
+                                                          L.s[cur ^ 1], nch, centre_r, mrow, d1, d2, slr);
                     end_step(k + h, d1, d2);
                 }
             }
@@ -2365,6 +2579,10 @@ __global__ void zero_ints_kernel(int *p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
+__global__ void zero_doubles_kernel(double *p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
 __global__ void weights_kernel(const double *mom, const double *ctab, double *W, long long nd, int npl) {
     const int nq = npl + 1;
     const long long total = nd * nq;
@@ -2686,6 +2904,18 @@ hipError_t launch_moments_t(const LaunchArgs &a, int nch, bool mixed, int nwg, h
     });
 }
 template <int c>
+hipError_t launch_forces_t(const LaunchArgs &a, int nch, int nwg, hipStream_t s) {
+    if constexpr (!Shape<c>::STREAM) {
+        return with_chains<c>(nch, [&](auto ncht) {
+            constexpr int NCH = decltype(ncht)::value;
+            hipLaunchKernelGGL((forces_ring_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            return hipGetLastError();
+        });
+    } else {
+        return hipErrorInvalidValue;  // forces: resident cubes only
+    }
+}
+template <int c>
 hipError_t occupancy_t(bool lanczos, bool mixed, int nch, int *nb) {
     const int B = Shape<c>::BLOCK;
     return with_chains<c>(nch, [&](auto ncht) {
@@ -2709,6 +2939,9 @@ hipError_t occupancy_t(bool lanczos, bool mixed, int nch, int *nb) {
     hipError_t moments_c##c(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s) {     \
         return launch_moments_t<c>(a, nch, mixed, nwg, s);                                          \
     }                                                                                               \
+    hipError_t forces_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s) {                  \
+        return launch_forces_t<c>(a, nch, nwg, s);                                                  \
+    }                                                                                               \
     hipError_t occupancy_c##c(bool lanczos, bool mixed, int nch, int *nb) {                         \
         return occupancy_t<c>(lanczos, mixed, nch, nb);                                             \
     }                                                                                               \
@@ -2725,6 +2958,7 @@ SQ_ALL_CUBES
 #define X(c)                                                                         \
     hipError_t lanczos_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s);  \
     hipError_t moments_c##c(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s); \
+    hipError_t forces_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s);   \
     hipError_t occupancy_c##c(bool lanczos, bool mixed, int nch, int *nb);          \
     int block_c##c();
 SQ_ALL_CUBES
@@ -2766,6 +3000,15 @@ hipError_t launch_moments(const LaunchArgs &a, int C, int nch, bool mixed, int n
     }
 }
 
+hipError_t launch_forces(const LaunchArgs &a, int C, int nch, int nwg, hipStream_t s) {
+    switch (C) {
+#define X(c) case c: return forces_c##c(a, nch, nwg, s);
+        SQ_ALL_CUBES
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+}
+
 namespace {
 static int grid_for(long long work, int block) {
     long long g = (work + block - 1) / block;
@@ -2785,6 +3028,11 @@ hipError_t launch_set_bounds(const double *lmin, const double *lmax, double *chi
 
 hipError_t launch_zero_ints(int *p, int n, hipStream_t s) {
     hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_doubles(double *p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_doubles_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -66,6 +66,7 @@ def load_library():
     lib.sq_fermi_level.argtypes = [P, P, D, dp, P]
     lib.sq_density_energy.argtypes = [P, P, D, P, dp, P]
     lib.sq_density_energy_static.argtypes = [P, P, D, P, dp, P]
+    lib.sq_nl_forces.argtypes = [P, D, dp, P]
     lib.sq_destroy.argtypes = [P]
     lib.sq_destroy.restype = None
     lib.sq_batch_default_options.argtypes = [ct.POINTER(BatchOptions)]
@@ -81,7 +82,7 @@ def load_library():
     lib.sq_batch_destroy.restype = None
     for name in ("sq_setup", "sq_query", "sq_bind", "sq_update_veff", "sq_spectral_bounds",
                  "sq_set_bounds", "sq_moments", "sq_fermi_level", "sq_density_energy",
-                 "sq_density_energy_static",
+                 "sq_density_energy_static", "sq_nl_forces",
                  "sq_batch_create", "sq_batch_query", "sq_batch_bind", "sq_batch_step",
                  "sq_batch_autotune", "sq_batch_tiles"):
         getattr(lib, name).restype = ct.c_int
@@ -123,6 +124,7 @@ class SQ:
         atoms = np.ascontiguousarray(np.asarray(atoms, dtype=np.float64).reshape(-1, 3))
         kb = np.ascontiguousarray(np.asarray(kb, dtype=np.float64).reshape(-1, 3))
         natom = atoms.shape[0]
+        self.natom = natom
         ctx = ct.c_void_p()
         dp = ct.POINTER(ct.c_double)
         _check(lib.sq_setup(ct.byref(ctx), float(cell), float(h), int(fd_order), float(rcut), int(npl),
@@ -221,6 +223,14 @@ class SQ:
         _check(_lib.sq_density_energy_static(self._ctx, _dptr(moments), float(mu), _dptr(rho), e,
                                              self._stream_ptr()))
         return rho, np.array(list(e))
+
+    def nl_forces(self, mu):
+        """sq_nl_forces: nonlocal atomic forces (natom x 3, Ha/Bohr) at Fermi
+        level mu and the current bounds."""
+        f = np.zeros((self.natom, 3))
+        _check(_lib.sq_nl_forces(self._ctx, float(mu), f.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                 self._stream_ptr()))
+        return f
 
     def scf_pass(self, n_electrons):
         """bounds -> moments -> Fermi level -> density and energies (fixed V_eff)."""
