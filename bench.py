@@ -154,6 +154,42 @@ def reuse_pass(g, bounds, n_electrons):
     return time.perf_counter() - t0
 
 
+def projector_nodes(wl) -> int:
+    """Grid nodes inside at least one projector sphere (|x - R| <= r_c on the
+    periodic grid): the nodes that carry nonlocal force contributions."""
+    from paper_1708_07913_amd import workloads as W
+    n = W.grid_points_per_axis(wl.cell, wl.h)
+    h = wl.cell / n
+    hit = np.zeros(n ** 3, dtype=bool)
+    for R, (_, rc, _) in zip(np.asarray(wl.atoms, float), np.asarray(wl.kb, float)):
+        r = int(np.ceil(rc / h)) + 1
+        b = np.floor(R / h).astype(int)
+        d = np.arange(-r, r + 2)
+        ii, jj, kk = np.meshgrid(b[0] + d, b[1] + d, b[2] + d, indexing="ij")
+        pts = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], 1)
+        inside = (((pts * h - R) ** 2).sum(1) <= rc * rc)
+        loc = np.mod(pts[inside], n)
+        hit[loc[:, 0] + n * (loc[:, 1] + n * loc[:, 2])] = True
+    return int(hit.sum())
+
+
+def forces_leg(g, wl, mu):
+    """One sq_nl_forces call (nonlocal forces, recurrence to n_pl) at the last
+    pass's bounds and Fermi level, timed on the host around the synchronising
+    call."""
+    t0 = time.perf_counter()
+    F = g.nl_forces(mu)
+    sec = time.perf_counter() - t0
+    nodes = projector_nodes(wl)
+    C = 2 * g.m + 1
+    node_steps = nodes * wl.npl
+    # per node-step: t^k, t^{k-1} in, t^{k+1} out, u in and out
+    nbytes = node_steps * 5 * C ** 3 * 8
+    return {"seconds": sec, "nodes": nodes, "node_steps": node_steps, "node_steps_per_s": node_steps / sec,
+            "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / sec / 1e9,
+            "max_abs_force_Ha_per_bohr": float(np.abs(F).max())}
+
+
 def golden_path(wl):
     names = {"al256_h0.4_rc6": "paper", "al1372_h0.5_rc7": "large"}
     if wl.name not in names:
@@ -402,6 +438,10 @@ def main():
           f"fermi {ph[2]:.1f} density {ph[3]:.1f}")
     reuse_s = reuse_pass(g, bounds, wl.n_electrons)
     log(f"pass reusing bounds: {reuse_s:.2f} s")
+    forces = None
+    if C <= 31 and wl.npl <= 256:
+        forces = forces_leg(g, wl, mu)
+        log(f"nonlocal forces: {forces['seconds']:.2f} s over {forces['nodes']} nodes")
 
     # dominant kernel and its roofline (algorithmic bytes: 3 N_s words per node-step)
     lanczos_bytes = nd * 50 * 3 * ns * 8
@@ -443,6 +483,8 @@ def main():
            # the same kernels against the bandwidth a plain copy reaches on this GPU
            "stencil_roofline_measured_bw": roof_meas,
            "electron_count": float(en[3]), "mu": mu}
+    if forces is not None:
+        rec["nl_forces"] = forces
     del mom, rho
 
     gm = None
