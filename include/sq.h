@@ -214,6 +214,13 @@ typedef struct sq_batch_options {
                             no eigenvalue moves further than max|delta V|); otherwise,
                             or if a moment leaves [-1, 1], the pass computes fresh
                             bounds. */
+    int reuse_check;     /* 1 (default): the V_eff change test above runs before
+                            bounds are reused; 0: reused bounds are trusted (for
+                            callers that bound the change of V_eff themselves), and a
+                            pass in which a moment leaves [-1, 1] is redone with fresh
+                            bounds.  That test only catches escapes the moments
+                            amplify past 1, which at low n_pl a moderate escape
+                            need not do. */
 } sq_batch_options;
 
 void sq_batch_default_options(sq_batch_options *opt);

@@ -1158,6 +1158,7 @@ void sq_batch_default_options(sq_batch_options *opt) {
     opt->wg_per_cu = 0;
     opt->use_graph = 1;
     opt->bounds_every = 1;
+    opt->reuse_check = 1;
 }
 
 int sq_batch_create(sq_batch **out, sq_ctx *const *ctxs, int n, double *const *moments, double *const *rho,
@@ -1307,7 +1308,7 @@ int sq_batch_step(sq_batch *b, double *mu, double *energies, void *stream) {
         // ones whose margin slack the batch recorded
         for (size_t i = 0; !bounds && i < b->ctx.size(); ++i)
             if (b->ctx[i]->bounds_gen != b->gen_seen[i]) bounds = true;
-        if (!bounds) {
+        if (!bounds && b->opt.reuse_check) {
             bool safe = false;
             rc = reuse_is_safe(b, b->own, &safe);
             if (rc) return rc;

@@ -36,7 +36,7 @@ class Options(ct.Structure):
 
 class BatchOptions(ct.Structure):
     _fields_ = [("block_nodes", ct.c_int), ("wg_per_cu", ct.c_int), ("use_graph", ct.c_int),
-                ("bounds_every", ct.c_int)]
+                ("bounds_every", ct.c_int), ("reuse_check", ct.c_int)]
 
 
 _lib = None
@@ -247,7 +247,7 @@ class Batch:
     of them (persistent work-queue launches; optionally one hipGraph)."""
 
     def __init__(self, snaps, n_electrons, block_nodes=0, wg_per_cu=0, use_graph=True, bounds_every=1,
-                 stream=None):
+                 stream=None, reuse_check=True):
         import torch
         lib = load_library()
         self.torch = torch
@@ -261,6 +261,7 @@ class Batch:
         lib.sq_batch_default_options(ct.byref(opt))
         opt.block_nodes, opt.wg_per_cu, opt.use_graph = int(block_nodes), int(wg_per_cu), int(bool(use_graph))
         opt.bounds_every = int(bounds_every)
+        opt.reuse_check = int(bool(reuse_check))
         ctxs = (ct.c_void_p * n)(*[s._ctx for s in self.snaps])
         mom = (ct.c_void_p * n)(*[t.data_ptr() for t in self.moments])
         rho = (ct.c_void_p * n)(*[t.data_ptr() for t in self.rho])

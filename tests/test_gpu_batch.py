@@ -219,3 +219,29 @@ def test_batch_bounds_reuse_across_veff_update():
     set_veff(3.0)
     mu, e = b.step()
     check_fresh(mu, e)
+
+
+def test_batch_redo_when_reused_bounds_fail():
+    """reuse_check = 0: the batch trusts its previous bounds after V_eff is
+    shifted down by 30 Ha, so every eigenvalue leaves the old interval and the
+    moments leave [-1, 1] (SQ_EBOUNDS inside the pass); the pass is redone
+    with fresh bounds and matches a fresh single-snapshot pass.  (A moderate
+    escape can keep every moment within [-1, 1] at low n_pl, which is why the
+    V_eff change test is on by default.)"""
+    sq = _sq()
+    wls = _small_ensemble()[:2]
+    print("case bounds redo", flush=True)
+    snaps = _snaps(wls)
+    refs = _snaps(wls)
+    b = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=True, bounds_every=1000, reuse_check=False)
+    b.step()
+    for g, r, wl in zip(snaps, refs, wls):
+        v = torch.from_numpy(wl.veff() - 30.0).cuda()
+        g.update_veff(v)
+        r.update_veff(v)
+    mu, e = b.step()
+    for i, (r, wl) in enumerate(zip(refs, wls)):
+        mom1, mu1, rho1, e1 = r.scf_pass(wl.n_electrons)
+        assert abs(mu[i] - mu1) < 1e-11, (mu[i], mu1)
+        assert np.abs(_np(b.rho[i]) - _np(rho1)).max() < 1e-12 * _np(rho1).max()
+        assert abs(e[i][3] - wl.n_electrons) < 1e-10 * wl.n_electrons
