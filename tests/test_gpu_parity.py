@@ -176,6 +176,36 @@ def test_mixed_precision_sweep(kT, npl):
     assert abs(e2[3] - wl.n_electrons) < 1e-9 * wl.n_electrons
 
 
+@pytest.mark.parametrize("kT", [0.5, 1.0])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_long_recurrence_npl320(kT, precision):
+    """n_pl = 320 (160 recurrence steps, the length of the paper's ambient-
+    temperature runs) on the tiny cell, against the FP64 oracle at its bounds
+    and Fermi level: FP64 to 1e-10, FP32-mixed to 1e-5 in rho and 1e-6 Ha per
+    atom, so the FP32 rounding does not grow past the bar over the longer
+    recurrence."""
+    sq = _sq()
+    wl = W.tiny_cell(precision=precision, npl=320, kT_eV=kT)
+    print(f"case {precision} kT={kT} npl=320", flush=True)
+    V, ref, g = _pair(wl, precision=sq.FP64 if precision == "fp64" else sq.FP32_MIXED)
+    lmin, lmax = ref.bounds()
+    mom_ref = ref.moments(lmin, lmax)
+    mu_ref, _ = ref.fermi_level(lmin, lmax, mom_ref, wl.n_electrons)
+    rho_ref, e_ref = ref.density_energy(lmin, lmax, mom_ref, mu_ref)
+    g.set_bounds(torch.from_numpy(lmin), torch.from_numpy(lmax))
+    mom = g.moments()
+    rho, e = g.density_energy(mom, mu_ref)
+    err = np.abs(_np(rho) - rho_ref).max() / rho_ref.max()
+    de = max(abs(e[0] - e_ref[0]), abs(e[2] - e_ref[2])) / wl.natom
+    print(f"{precision} kT={kT} npl=320: rho {err:.2e}  dE/atom {de:.2e}", flush=True)
+    if precision == "fp64":
+        assert np.abs(_np(mom) - mom_ref).max() < 1e-10
+        assert err < 1e-10
+    else:
+        assert err < 1e-5, err
+        assert de < 1e-6, de
+
+
 def _sampled_parity(wl, nsample, seed=0):
     V, ref, g = _pair(wl)
     nd = g.nd
