@@ -64,7 +64,7 @@ struct sq_ctx {
     int pstride = 0;    // doubles between a projector value and the one a plane above
     int max_overlap = 0;
     size_t off_atoms = 0, off_runs = 0, off_pvals = 0, off_chi = 0, off_zeta = 0, off_ctab = 0,
-           off_rk = 0, off_W = 0, off_part = 0, off_scal = 0, off_flags = 0, off_v32 = 0, off_forces = 0,
+           off_rk = 0, off_W = 0, off_part = 0, off_scal = 0, off_flags = 0, off_forces = 0,
            off_slots = 0, off_wslots = 0, off_xslots = 0, off_args = 0, total = 0;
     sq::RecurrenceArgs args_host[2] = {};  // staged launch arguments (Lanczos, moments)
     char *ws = nullptr;
@@ -228,7 +228,6 @@ sq::RecurrenceArgs recurrence_args(sq_ctx *c) {
     a.nd = c->nd;
     for (int d = 0; d <= sq::kNoMax; ++d) a.w[d] = c->w[d];
     a.veff = c->veff;
-    a.veff32 = c->opt.precision == SQ_FP32_MIXED ? c->at<float>(c->off_v32) : nullptr;
     a.natom = int(c->atoms.size());
     a.atoms = c->at<sq::AtomDev>(c->off_atoms);
     a.runs = c->at<sq::RunDev>(c->off_runs);
@@ -316,7 +315,6 @@ void layout(sq_ctx *c) {
     c->off_flags = take(64);
     c->off_forces = take(c->atoms.size() * 3 * sizeof(double));
     c->off_args = take(2 * sizeof(sq::RecurrenceArgs));
-    c->off_v32 = take(c->opt.precision == SQ_FP32_MIXED ? size_t(c->nd) * sizeof(float) : 0);
     // one slot per workgroup: C planes of slot_plane(C) doubles
     const size_t se = size_t(sq::slot_elems_for(c->C));
     c->off_slots = take(size_t(c->nwg_slots) * se * sizeof(double));
@@ -328,12 +326,8 @@ void layout(sq_ctx *c) {
     c->total = off;
 }
 
-int upload_veff(sq_ctx *c, const double *veff, hipStream_t s) {
-    c->veff = veff;
-    if (c->opt.precision == SQ_FP32_MIXED) {
-        int rc = hip_check(sq::launch_to_fp32(veff, c->at<float>(c->off_v32), c->nd, s), "V_eff to FP32");
-        if (rc) return rc;
-    }
+int upload_veff(sq_ctx *c, const double *veff, hipStream_t) {
+    c->veff = veff;  // read in FP64 by every kernel (the mixed one included)
     return SQ_OK;
 }
 

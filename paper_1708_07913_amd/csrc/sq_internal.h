@@ -68,7 +68,6 @@ struct RecurrenceArgs {
     long long nd;
     double w[kNoMax + 1];   // FD Laplacian weights w_0..w_6 (zero beyond n_o)
     const double *veff;     // n^3 FP64
-    const float *veff32;    // n^3 FP32 copy (mixed precision)
     int natom;
     const AtomDev *atoms;
     const RunDev *runs;
@@ -274,7 +273,6 @@ int recurrence_block(int C);
 hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int nch, int *blocks_per_cu);
 hipError_t launch_set_bounds(const double *lmin, const double *lmax, double *chi, double *zeta,
                              long long nd, double margin, hipStream_t s);
-hipError_t launch_to_fp32(const double *src, float *dst, long long n, hipStream_t s);
 hipError_t launch_quadrature_weights(const double *mom, const double *ctab, double *W,
                                      long long nd, int npl, hipStream_t s);
 hipError_t launch_extent(const double *chi, const double *zeta, long long nd, double *partials,

@@ -93,7 +93,9 @@ struct Shape {
     // wider regions stream it through the workgroup's buffers with a window of
     // 2 NO + 2 planes in registers
     static constexpr bool STREAM = C > kResidentCube;
-    // plane buffers: resident cubes sweep Lanczos two planes per barrier
+    // plane buffers: two for the streamed kernels (one plane per barrier);
+    // four for the register-ring kernels, which use two, or all four when
+    // built with two planes per barrier (SQ_RING_PPB=2)
     static constexpr int NBUF = STREAM ? 2 : 4;
     static constexpr int CPT = (CC + BLOCK - 1) / BLOCK;     // columns per thread in the set-up scan
 };
@@ -808,25 +810,21 @@ struct WorkSource {
 //   t^0 = e_q, t^1 = Hhat t^0, t^{k+1} = 2 Hhat t^k - t^{k-1},
 //   rho^j = t^j[q] (j <= n_pl/2), rho^{2k} = 2 t^k.t^k - rho^0,
 //   rho^{2k-1} = 2 t^k.t^{k-1} - rho^1 (k > n_pl/4).
-// Three storage modes of the vectors (chosen by cube size and precision):
-//   FP64, resident: t^k and t^{k+1} in registers, t^{k-1} streamed through
-//     the workgroup's slot (read and overwritten by t^k plane by plane);
-//   FP32-mixed, resident: t^{k-1} also in registers, overwritten in place by
-//     t^{k+1}, so no vector moves through memory;
-//   streamed (cubes wider than kResidentCube): t^k read from buffer X with a
-//     look-ahead of NO + 1 planes, t^{k-1} read from buffer Y and replaced
-//     there by t^{k+1}; X and Y swap roles every step.
-// Global loads of plane z + 1 (potential window, t^{k-1}, projector values)
-// are issued during plane z.
+// This kernel serves the cubes wider than kResidentCube (both precisions;
+// narrower cubes run the register-ring kernels below): t^k is read from
+// buffer X with a look-ahead of NO + 1 planes, t^{k-1} is read from buffer Y
+// and replaced there by t^{k+1}; X and Y swap roles every step.  Global loads
+// of plane z + 1 (potential window, t^{k-1}, projector values) are issued
+// during plane z.
 // ---------------------------------------------------------------------------
-template <int C, typename T, int NCH>
+template <int C, int NCH>
 __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) {
     using S = Shape<C>;
+    using T = double;
     constexpr int RB = S::RB;
     constexpr int MC = (C - 1) / 2;
-    constexpr bool kStream = S::STREAM;
-    constexpr bool kResident = !kStream && sizeof(T) == 4;  // t^{k-1} held in registers
-    constexpr int ZA = NO + 1;                               // look-ahead of the streamed t^k
+    constexpr int ZA = NO + 1;  // look-ahead of the streamed t^k
+    static_assert(S::STREAM, "streamed cubes only");
     __shared__ Lds<C, T, NCH> L;
     const int tid = threadIdx.x;
     Cols<C> cl;
@@ -838,8 +836,8 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
     const long long slot_bytes = K.slot_elems * (long long)sizeof(T);
     __amdgpu_buffer_rsrc_t slr =
         make_rsrc(reinterpret_cast<T *>(K.slots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
-    __amdgpu_buffer_rsrc_t sly = slr;
-    if (kStream) sly = make_rsrc(reinterpret_cast<T *>(K.wslots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
+    __amdgpu_buffer_rsrc_t sly =
+        make_rsrc(reinterpret_cast<T *>(K.wslots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
     unsigned voff[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * (unsigned)sizeof(T) : kIdleOffset;
@@ -851,7 +849,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
     const auto &A = *Ap;
     const int n = A.n;
     const int npl = A.npl, half = npl / 2;
-    const __amdgpu_buffer_rsrc_t vr = sizeof(T) == 4 ? make_rsrc(A.veff32, A.nd * 4) : make_rsrc(A.veff, A.nd * 8);
+    const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
     const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
     const double kin0 = -3.0 * A.w[0];
 
@@ -878,23 +876,13 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
         double *mrow = A.moments + q * (long long)(npl + 1);
         auto e_q = [&](int r, int z) { return T((centre_r == r && z == MC) ? 1 : 0); };
 
-        T tv[RB][C];   // t^k (streamed mode: a window of planes)
-        T tp[RB][C];   // t^{k-1}, overwritten by t^{k+1} (FP32 resident mode only)
-        if (!kStream) {
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-#pragma unroll
-                for (int z = 0; z < C; ++z) {
-                    tv[r][z] = e_q(r, z);
-                    tp[r][z] = T(0);
-                }
-        }
+        T tv[RB][C];  // a window of planes of t^k
         if (tid == 0) mrow[0] = 1.0;
         int cur = 0;
-        // streamed mode: t^0 goes to X here, so that every sweep reads X
+        // t^0 goes to X here, so that every sweep reads X
         projector_dots<false>(L, pvr, cl, cur, nch, [&](int r, int z) {
             const T v = e_q(r, z);
-            if (kStream) bstore(v, slr, voff[r], (unsigned)(z * S::CC) * (unsigned)sizeof(T));
+            bstore(v, slr, voff[r], (unsigned)(z * S::CC) * (unsigned)sizeof(T));
             return (double)v;
         });
 
@@ -910,16 +898,13 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
             double d1 = 0.0, d2 = 0.0;
             unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
             asm volatile("" : "+s"(zb));  // keep the per-plane offsets inside the step loop
-            const bool stream_prev = !kResident && k > 0;
-            // streamed t^k: the first planes of the window
-            if (kStream) {
+            const bool stream_prev = k > 0;
+            // t^k: the first planes of the window
 #pragma unroll
-                for (int z = 0; z < (ZA < C ? ZA : C); ++z)
+            for (int z = 0; z < (ZA < C ? ZA : C); ++z)
 #pragma unroll
-                    for (int r = 0; r < RB; ++r)
-                        tv[r][z] = bload<T>(slr, voff[r], (unsigned)(z * S::CC) * (unsigned)sizeof(T));
-            }
-            T nv[RB][C];
+                for (int r = 0; r < RB; ++r)
+                    tv[r][z] = bload<T>(slr, voff[r], (unsigned)(z * S::CC) * (unsigned)sizeof(T));
             // plane 0 loads; plane z + 1 is loaded while plane z is processed
             double vzn[RB], tpn[RB];
 #pragma unroll
@@ -935,7 +920,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
                     vz[r] = vzn[r];
-                    tprev[r] = kResident ? (double)tp[r][z] : tpn[r];
+                    tprev[r] = tpn[r];
                     if (z + 1 < C) {
                         const unsigned sz1 = (unsigned)((z + 1) * S::CC) * (unsigned)sizeof(T);
                         const unsigned vz1 = (unsigned)(n * n) * ((zb + (unsigned)(z + 1)) % (unsigned)n) *
@@ -943,7 +928,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
                         vzn[r] = (double)bload<T>(vr, vcol[r], vz1);
                         if (stream_prev) tpn[r] = (double)bload<T>(sly, voff[r], sz1);
                     }
-                    if (kStream && z + ZA < C)
+                    if (z + ZA < C)
                         tv[r][z + ZA] = bload<T>(slr, voff[r], (unsigned)((z + ZA) * S::CC) * (unsigned)sizeof(T));
                     L.plane[z & 1][cl.pcw[r]] = tv[r][z];
                 }
@@ -970,20 +955,8 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
                     // a real column; it must stay zero, since it is that column's
                     // y neighbour
                     if (!cl.valid(r)) nvd = 0.0;
-                    // the moment t^{k+1}[q] is taken before the vector is
-                    // stored: with FP32 storage its rounding would otherwise
-                    // enter rho^{k+1} directly (and alike for every node)
                     const double moment = nvd;
-                    const T nvt = T(nvd);
-                    nvd = (double)nvt;
-                    if (kResident) {
-                        tp[r][z] = nvt;
-                    } else if (kStream) {
-                        bstore(nvt, sly, voff[r], sz);  // t^{k+1} over t^{k-1}
-                    } else {
-                        nv[r][z] = nvt;
-                        bstore(tv[r][z], slr, voff[r], sz);
-                    }
+                    bstore(nvd, sly, voff[r], sz);  // t^{k+1} over t^{k-1}
                     d1 += nvd * nvd;
                     d2 += nvd * tz;
                     pin(d1);
@@ -1016,24 +989,11 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_kernel(LaunchArgs K) 
                         atomicOr(A.flags, kFlagBounds);
                 }
             }
-            // t^k -> t^{k-1}, t^{k+1} -> t^k
-            if (kStream) {
+            // t^k -> t^{k-1}, t^{k+1} -> t^k: X and Y swap
+            {
                 const __amdgpu_buffer_rsrc_t t = slr;
                 slr = sly;
                 sly = t;
-            } else {
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-#pragma unroll
-                    for (int z = 0; z < C; ++z) {
-                        if (kResident) {
-                            const T t = tv[r][z];
-                            tv[r][z] = tp[r][z];
-                            tp[r][z] = t;
-                        } else {
-                            tv[r][z] = nv[r][z];
-                        }
-                    }
             }
             for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) L.s[cur][i] = 0.0;
             cur ^= 1;
@@ -1105,33 +1065,32 @@ __device__ void sturm_extremes(int k, const double *a, const double *b, double *
     if (j == 0) out[half] = hi;
 }
 
-// Resident cubes keep v_j in registers; the sweep writes v_j to the slot (it
-// is v_{j-1} of the next step) and u to wslot, and the second pass rebuilds
-// w = u - alpha v_j in the registers.  Streamed cubes keep w_j (not yet
-// divided by beta_j) in buffer X and v_{j-1} (as stored w_{j-1}) in buffer Y,
-// read with a look-ahead window and scaled on load; the second pass writes w
-// over Y and the two buffers swap roles.
+// Cubes wider than kResidentCube (narrower ones run lanczos_ring_kernel):
+// w_j (not yet divided by beta_j) sits in buffer X and v_{j-1} (as the stored
+// w_{j-1}) in buffer Y, both read with a look-ahead window and scaled on load.
+// The sweep writes the local part u of H v_j - beta_{j-1} v_{j-1} to a third
+// buffer; a second pass adds the projector part, forms w = u - alpha v_j over
+// Y, and the two buffers swap roles.
 template <int C, int NCH>
 __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) {
     using S = Shape<C>;
     using T = double;
     constexpr int RB = S::RB;
-    constexpr bool kStream = S::STREAM;
     constexpr int ZA = NO + 1;
+    static_assert(S::STREAM, "streamed cubes only");
     __shared__ Lds<C, T, NCH> L;
     __shared__ LanczosLds LL;
     const int tid = threadIdx.x;
     Cols<C> cl;
     cl.init(tid);
     const long long slot_bytes = K.slot_elems * 8;
-    // resident: slr holds v_{j-1}, overwritten by v_j during the sweep.
-    // streamed: slr = X (current), sly = Y (previous).  wlr: u = H v_j - beta v_{j-1}
+    // slr = X (current), sly = Y (previous); wlr: u = H v_j - beta v_{j-1}
     __amdgpu_buffer_rsrc_t slr =
         make_rsrc(reinterpret_cast<T *>(K.slots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
     const __amdgpu_buffer_rsrc_t wlr =
         make_rsrc(reinterpret_cast<T *>(K.wslots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
-    __amdgpu_buffer_rsrc_t sly = slr;
-    if (kStream) sly = make_rsrc(reinterpret_cast<T *>(K.xslots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
+    __amdgpu_buffer_rsrc_t sly =
+        make_rsrc(reinterpret_cast<T *>(K.xslots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
     unsigned voff[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * 8u : kIdleOffset;
@@ -1170,25 +1129,18 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
             return cl.valid(r) ? (unit_from_seed((unsigned long long)(cl.col[r] + C * C * z)) - 0.5) * rnorm : 0.0;
         };
 
-        double tv[RB][C];  // v_j (streamed mode: a window of planes)
-        if (!kStream) {
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-#pragma unroll
-                for (int z = 0; z < C; ++z) tv[r][z] = start(r, z);
-        }
+        double tv[RB][C];  // a window of planes of v_j
         int cur = 0;
-        // streamed mode: v_1 goes to X here, so that every sweep reads X
+        // v_1 goes to X here, so that every sweep reads X
         projector_dots<true>(L, pvr, cl, cur, nch, [&](int r, int z) {
-            if (!kStream) return tv[r][z];
             const double v = start(r, z);
             bstore(v, slr, voff[r], (unsigned)(z * S::CC) * 8u);
             return v;
         });
 
         double bprev = 0.0, gersh = 0.0;
-        // v_j = scx * (register columns, or X when streamed), v_{j-1} = scy * slot
-        // (or Y): the vectors are kept as w = u - alpha v, not divided by beta
+        // v_j = scx * X, v_{j-1} = scy * Y: the vectors are kept as
+        // w = u - alpha v, not divided by beta
         double scx = 1.0, scy = 0.0;
         int ksteps = kmax;
         for (int j = 0; j < kmax; ++j) {
@@ -1200,17 +1152,14 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
                 L.cs[i] = i < ni ? L.img_coef[i] * L.s[cur][i] : 0.0;
             unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
             asm volatile("" : "+s"(zb));
-            const __amdgpu_buffer_rsrc_t prev = kStream ? sly : slr;
+            const __amdgpu_buffer_rsrc_t prev = sly;
             const double sprev = scy;
-            if (kStream) {
 #pragma unroll
-                for (int z = 0; z < (ZA < C ? ZA : C); ++z)
+            for (int z = 0; z < (ZA < C ? ZA : C); ++z)
 #pragma unroll
-                    for (int r = 0; r < RB; ++r) tv[r][z] = bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u);
-            }
-            // PPB planes per barrier (resident cubes: two, with four plane
-            // buffers); the loads of the next group are issued while this
-            // group is processed
+                for (int r = 0; r < RB; ++r) tv[r][z] = bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u);
+            // PPB planes per barrier (one: two plane buffers); the loads of
+            // the next plane are issued while this one is processed
             constexpr int PPB = S::NBUF / 2;
             double da = 0.0;
             double vzn[PPB][RB], vpn[PPB][RB];
@@ -1247,7 +1196,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
                     if (z < C) {
 #pragma unroll
                         for (int r = 0; r < RB; ++r) {
-                            if (kStream && z + ZA < C)
+                            if (z + ZA < C)
                                 tv[r][z + ZA] = bload<double>(slr, voff[r], (unsigned)((z + ZA) * S::CC) * 8u);
                             L.plane[pb + h][cl.pcw[r]] = tv[r][z];
                         }
@@ -1267,7 +1216,6 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
                             double u = scx * (stencil_sum<C, double>(pv, yrow, tv[r], r, z, kw) + (vz[h][r] + kin0) * tv[r][z]);
                             u -= bprev * vprev[h][r];
                             if (!cl.valid(r)) u = 0.0;  // column past the cube edge stays zero
-                            if (!kStream) bstore(tv[r][z], slr, voff[r], sz);
                             bstore(u, wlr, voff[r], sz);
                             da += u * tv[r][z];
                             pin(da);
@@ -1295,7 +1243,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
 #pragma unroll
                 for (int ci = 0; ci < NCH; ++ci) ch[r][ci].c = L.cs[ch[r][ci].sl()];
             }
-            // u (and, streamed, v_j) loads run LA planes ahead
+            // u and v_j loads run LA planes ahead
             constexpr int LA = 3;
             double un[LA][RB], xn[LA][RB];
 #pragma unroll
@@ -1303,8 +1251,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
 #pragma unroll
                 for (int z = 0; z < LA; ++z) {
                     un[z][r] = z < C ? bload<double>(wlr, voff[r], (unsigned)(z * S::CC) * 8u) : 0.0;
-                    xn[z][r] = 0.0;
-                    if (kStream && z < C) xn[z][r] = bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u);
+                    xn[z][r] = z < C ? bload<double>(slr, voff[r], (unsigned)(z * S::CC) * 8u) : 0.0;
                 }
             }
 #pragma unroll
@@ -1312,19 +1259,18 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
                     double uz = un[z % LA][r];
-                    const double vj = scx * (kStream ? xn[z % LA][r] : tv[r][z]);
+                    const double vj = scx * xn[z % LA][r];
                     if (z + LA < C) {
                         const unsigned sz2 = (unsigned)((z + LA) * S::CC) * 8u;
                         un[z % LA][r] = bload<double>(wlr, voff[r], sz2);
-                        if (kStream) xn[z % LA][r] = bload<double>(slr, voff[r], sz2);
+                        xn[z % LA][r] = bload<double>(slr, voff[r], sz2);
                     }
 #pragma unroll
                     for (int ci = 0; ci < NCH; ++ci)
                         if (ci == 0 || ci < nch) uz += ch[r][ci].c * ch[r][ci].pv[z & 1];
                     double w = uz - alpha * vj;
                     if (!cl.valid(r)) w = 0.0;
-                    if (kStream) bstore(w, sly, voff[r], (unsigned)(z * S::CC) * 8u);
-                    else tv[r][z] = w;
+                    bstore(w, sly, voff[r], (unsigned)(z * S::CC) * 8u);
                     db += w * w;
                     pin(db);
 #pragma unroll
@@ -1360,7 +1306,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_kernel(LaunchArgs K) 
                 break;
             }
             const double rb = uniform(1.0 / beta);
-            if (kStream) {
+            {
                 // X <- w_j, Y <- the buffer holding v_j
                 const __amdgpu_buffer_rsrc_t t = slr;
                 slr = sly;
@@ -2567,12 +2513,6 @@ __global__ void set_bounds_kernel(const double *lmin, const double *lmax, double
     }
 }
 
-__global__ void to_fp32_kernel(const double *src, float *dst, long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        dst[i] = (float)src[i];
-}
-
 // Fill of int counters (a kernel, not a memset, so that it can sit in a
 // captured graph).
 __global__ void zero_ints_kernel(int *p, int n) {
@@ -2860,8 +2800,8 @@ static __device__ __align__(256) double scratch[kStaticScratchDoubles];
 #define SQ_ALL_CUBES X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29) X(31) X(33) X(35) X(37)
 
 #ifndef SQ_COMMON_ONLY
+// Launchers.  Resident cubes (up to kResidentCube) run the register-ring
 // kernels in FP64 and moments_mixed_kernel in FP32-mixed mode, built for
-// kernels in FP64 and moments_kernel<c, float> in FP32-mixed mode, built for
 // 1, 2 or 4 projector chains.  Streamed cubes are built with two chains only
 // (the host rejects deeper sphere overlaps there) and run the FP64 streamed
 // kernels in both precisions: with the current vector streamed through
@@ -2898,7 +2838,7 @@ hipError_t launch_moments_t(const LaunchArgs &a, int nch, bool mixed, int nwg, h
             if (mixed) hipLaunchKernelGGL((moments_mixed_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
             else hipLaunchKernelGGL((moments_ring_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
         } else {
-            hipLaunchKernelGGL((moments_kernel<c, double, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            hipLaunchKernelGGL((moments_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
         }
         return hipGetLastError();
     });
@@ -2926,7 +2866,7 @@ hipError_t occupancy_t(bool lanczos, bool mixed, int nch, int *nb) {
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_ring_kernel<c, NCH>, B, 0);
         } else {
             if (lanczos) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, NCH>, B, 0);
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, double, NCH>, B, 0);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, NCH>, B, 0);
         }
     });
 }
@@ -3033,11 +2973,6 @@ hipError_t launch_zero_ints(int *p, int n, hipStream_t s) {
 
 hipError_t launch_zero_doubles(double *p, int n, hipStream_t s) {
     hipLaunchKernelGGL(zero_doubles_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_to_fp32(const double *src, float *dst, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(to_fp32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, src, dst, n);
     return hipGetLastError();
 }
 
