@@ -181,9 +181,8 @@ int sq_density_energy_static(sq_ctx *ctx, const double *moments, double mu, doub
  * with the recurrence run to n_pl (twice the density's length) at the
  * current bounds and the Chebyshev coefficients c_q^j of the Fermi function
  * at Fermi level mu (from sq_fermi_level).  FP64 in both precision modes.
- * Requires bounds (SQ_ESTATE otherwise), regions of at most 31 points per
- * side and n_pl <= 256 (SQ_EINVAL otherwise).  Uses the workspace's vector
- * buffers; synchronises `stream`. */
+ * Requires bounds (SQ_ESTATE otherwise) and n_pl <= 256 (SQ_EINVAL
+ * otherwise).  Uses the workspace's vector buffers; synchronises `stream`. */
 int sq_nl_forces(sq_ctx *ctx, double mu, double *forces, void *stream);
 
 /* Release the host tables (never touches caller-owned device memory). */

@@ -1119,8 +1119,6 @@ int sq_nl_forces(sq_ctx *c, double mu, double *forces, void *stream) {
         if (rc) return rc;
         if (!forces) return fail(SQ_EINVAL, "forces must be a host array of natom x 3 doubles");
         if (!is_finite(mu)) return fail(SQ_EINVAL, "mu must be finite");
-        if (c->C > sq::kResidentCube)
-            return fail(SQ_EINVAL, "nonlocal forces need regions of at most 31 points per side");
         if (c->nq > sq::kMaxForceNq) return fail(SQ_EINVAL, "nonlocal forces need n_pl <= 256");
         const size_t na = c->atoms.size();
         for (size_t i = 0; i < 3 * na; ++i) forces[i] = 0.0;

@@ -1767,6 +1767,104 @@ struct ForcesLds {
     int nc;
 };
 
+// The images whose sphere contains node q (the centre column's runs that
+// cover the centre plane) with p_I(q); cleared force sums.  Returns their
+// number (workgroup-uniform; ends on a barrier).
+template <int C, int NCH, typename AT>
+__device__ int forces_centre_images(const AT &A, const Lds<C, double, NCH> &L, ForcesLds &FL, int tid) {
+    constexpr int MC = (C - 1) / 2;
+    if (tid == 0) {
+        constexpr int cc = MC * C + MC;
+        int nc = 0;
+        for (int i = L.col_start[cc]; i < L.col_start[cc + 1] && i < Shape<C>::MAXRUNS; ++i) {
+            const uint2 rr = L.runs[i];
+            const int z0 = (int)((rr.x >> 8) & 0xFFu), z1 = (int)((rr.x >> 16) & 0xFFu);
+            if (z0 <= MC && MC <= z1 && nc < 4) {
+                FL.img[nc] = (int)(rr.x & 0xFFu);
+                FL.pc[nc] = A.pvals[(int)rr.y + MC * A.pstride];
+                ++nc;
+            }
+        }
+        FL.nc = nc;
+        for (int i = 0; i < 12; ++i) (&FL.fs[0][0])[i] = 0.0;
+    }
+    __syncthreads();
+    return FL.nc;
+}
+
+// c_q^j, j = 0 .. n_pl, by discrete orthogonality (Sec. 3.2): the Fermi
+// function at the quadrature nodes, then the coefficient table.  Ends on a
+// barrier.
+template <int C, typename AT>
+__device__ void forces_coefficients(const AT &A, ForcesLds &FL, double chi, double zeta, int tid) {
+    const int nq = A.npl + 1;
+    for (int k = tid; k < nq; k += Shape<C>::BLOCK)
+        FL.gk[k] = 1.0 / (1.0 + exp((zeta * A.rk[k] + chi - A.mu) / A.kT));
+    __syncthreads();
+    for (int j = tid; j < nq; j += Shape<C>::BLOCK) {
+        double c = 0.0;
+        for (int k = 0; k < nq; ++k) c += A.ctab[j * nq + k] * FL.gk[k];
+        FL.cj[j] = c;
+    }
+    __syncthreads();
+}
+
+// p_I^T grad_{h,q} u for the centre images (one thread per run record of a
+// centre image; u in cube-plane layout, complete in memory), then the forces
+// -4 gamma h^3 p_I(q) (p_I^T grad u) added to the atoms.
+template <int C, int NCH, typename AT>
+__device__ void forces_gradient(const AT &A, const Lds<C, double, NCH> &L, ForcesLds &FL, const double *ubuf,
+                                int tid) {
+    using S = Shape<C>;
+    const int ncent = FL.nc;
+    const int nrec = L.col_start[S::CC] < S::MAXRUNS ? L.col_start[S::CC] : S::MAXRUNS;
+    for (int i = tid; i < nrec; i += S::BLOCK) {
+        const uint2 rr = L.runs[i];
+        const int I = (int)(rr.x & 0xFFu);
+        int m = -1;
+        for (int mm = 0; mm < ncent; ++mm)
+            if (FL.img[mm] == I) m = mm;
+        if (m < 0) continue;
+        int lo = 0, hi = S::CC;  // column: last c with col_start[c] <= i
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (L.col_start[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        const int x = lo % C, y = lo / C;
+        const int z0 = (int)((rr.x >> 8) & 0xFFu), z1 = (int)((rr.x >> 16) & 0xFFu);
+        double g3[3] = {0.0, 0.0, 0.0};
+        for (int z = z0; z <= z1; ++z) {
+            const double p = A.pvals[(int)rr.y + z * A.pstride];
+            const double *uz = ubuf + (long long)z * S::CC + y * C + x;
+            double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+            for (int d = 1; d <= NO; ++d) {
+                const double w = A.gw[d];
+                if (x + d < C) gx += w * uz[d];
+                if (x - d >= 0) gx -= w * uz[-d];
+                if (y + d < C) gy += w * uz[d * C];
+                if (y - d >= 0) gy -= w * uz[-d * C];
+                if (z + d < C) gz += w * uz[d * S::CC];
+                if (z - d >= 0) gz -= w * uz[-d * S::CC];
+            }
+            g3[0] += p * gx;
+            g3[1] += p * gy;
+            g3[2] += p * gz;
+        }
+        atomicAdd(&FL.fs[m][0], g3[0]);
+        atomicAdd(&FL.fs[m][1], g3[1]);
+        atomicAdd(&FL.fs[m][2], g3[2]);
+    }
+    __syncthreads();
+    if (tid < 3 * ncent) {
+        const int m = tid / 3, ax = tid % 3, I = FL.img[m];
+        atomicAdd(&A.forces[3 * L.img_atom[I] + ax], -4.0 * L.img_coef[I] * FL.pc[m] * FL.fs[m][ax]);
+    }
+    __syncthreads();
+}
+
+
 template <int C, int NCH>
 __global__ __launch_bounds__(Shape<C>::BLOCK) void forces_ring_kernel(LaunchArgs K) {
     using S = Shape<C>;
@@ -1798,7 +1896,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void forces_ring_kernel(LaunchArgs
     while (work.next(K, L, tid, Ap, qfirst, qend, qstep)) {
     const auto &A = *Ap;
     const int n = A.n;
-    const int npl = A.npl, nq = npl + 1;
+    const int npl = A.npl;
     const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
     const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
     const double kin0 = -3.0 * A.w[0];
@@ -1807,40 +1905,13 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void forces_ring_kernel(LaunchArgs
         int qi, qj, qk;
         node_coords(q, n, qi, qj, qk);
         setup_region(A, L, qi, qj, qk, tid);
-        // images whose sphere contains the node: the centre column's runs
-        // that cover the centre plane
-        if (tid == 0) {
-            constexpr int cc = MC * C + MC;
-            int nc = 0;
-            for (int i = L.col_start[cc]; i < L.col_start[cc + 1] && i < S::MAXRUNS; ++i) {
-                const uint2 rr = L.runs[i];
-                const int z0 = (int)((rr.x >> 8) & 0xFFu), z1 = (int)((rr.x >> 16) & 0xFFu);
-                if (z0 <= MC && MC <= z1 && nc < 4) {
-                    FL.img[nc] = (int)(rr.x & 0xFFu);
-                    FL.pc[nc] = A.pvals[(int)rr.y + MC * A.pstride];
-                    ++nc;
-                }
-            }
-            FL.nc = nc;
-            for (int i = 0; i < 12; ++i) (&FL.fs[0][0])[i] = 0.0;
-        }
-        __syncthreads();
-        const int ncent = FL.nc;
-        if (ncent == 0) continue;
+        if (forces_centre_images(A, L, FL, tid) == 0) continue;
         const int ni = L.ni < kMaxImages ? L.ni : kMaxImages;
         const int nch = L.nch;
         const unsigned zbase = (unsigned)pmod(qk - A.m, n);
         const double chi = uniform(A.chi[q]), zeta = uniform(A.zeta[q]);
         const double invz = uniform(1.0 / zeta);
-        // c_q^j by discrete orthogonality (Sec. 3.2), j = 0 .. n_pl
-        for (int k = tid; k < nq; k += S::BLOCK)
-            FL.gk[k] = 1.0 / (1.0 + exp((zeta * A.rk[k] + chi - A.mu) / A.kT));
-        __syncthreads();
-        for (int j = tid; j < nq; j += S::BLOCK) {
-            double c = 0.0;
-            for (int k = 0; k < nq; ++k) c += A.ctab[j * nq + k] * FL.gk[k];
-            FL.cj[j] = c;
-        }
+        forces_coefficients<C>(A, FL, chi, zeta, tid);
         double kw[NO + 1];
         kw[0] = 0.0;
 #pragma unroll
@@ -1892,52 +1963,176 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void forces_ring_kernel(LaunchArgs
             step(k, std::true_type());
             step(k + 1, std::false_type());
         }
-        // p^T grad_{h,q} u for the centre images: one run record per thread
-        const int nrec = L.col_start[S::CC] < S::MAXRUNS ? L.col_start[S::CC] : S::MAXRUNS;
-        for (int i = tid; i < nrec; i += S::BLOCK) {
-            const uint2 rr = L.runs[i];
-            const int I = (int)(rr.x & 0xFFu);
-            int m = -1;
-            for (int mm = 0; mm < ncent; ++mm)
-                if (FL.img[mm] == I) m = mm;
-            if (m < 0) continue;
-            int lo = 0, hi = S::CC;  // column: last c with col_start[c] <= i
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (L.col_start[mid] <= i) lo = mid;
-                else hi = mid;
-            }
-            const int x = lo % C, y = lo / C;
-            const int z0 = (int)((rr.x >> 8) & 0xFFu), z1 = (int)((rr.x >> 16) & 0xFFu);
-            double g3[3] = {0.0, 0.0, 0.0};
-            for (int z = z0; z <= z1; ++z) {
-                const double p = A.pvals[(int)rr.y + z * A.pstride];
-                const double *uz = ubuf + (long long)z * S::CC + y * C + x;
-                double gx = 0.0, gy = 0.0, gz = 0.0;
+        forces_gradient(A, L, FL, ubuf, tid);
+    }
+    }
+}
+
+// Nonlocal forces on the streamed cubes (wider than kResidentCube): the
+// streamed recurrence of moments_kernel run to n_pl, with u accumulated in the
+// third buffer.
+template <int C, int NCH>
+__global__ __launch_bounds__(Shape<C>::BLOCK) void forces_kernel(LaunchArgs K) {
+    using S = Shape<C>;
+    using T = double;
+    constexpr int RB = S::RB;
+    constexpr int MC = (C - 1) / 2;
+    constexpr int ZA = NO + 1;  // look-ahead of the streamed t^k
+    static_assert(S::STREAM, "streamed cubes only");
+    __shared__ Lds<C, T, NCH> L;
+    __shared__ ForcesLds FL;
+    const int tid = threadIdx.x;
+    Cols<C> cl;
+    cl.init(tid);
+    int centre_r = -1;
 #pragma unroll
-                for (int d = 1; d <= NO; ++d) {
-                    const double w = A.gw[d];
-                    if (x + d < C) gx += w * uz[d];
-                    if (x - d >= 0) gx -= w * uz[-d];
-                    if (y + d < C) gy += w * uz[d * C];
-                    if (y - d >= 0) gy -= w * uz[-d * C];
-                    if (z + d < C) gz += w * uz[d * S::CC];
-                    if (z - d >= 0) gz -= w * uz[-d * S::CC];
+    for (int r = 0; r < RB; ++r)
+        if (cl.col[r] == MC * C + MC) centre_r = r;
+    const long long slot_bytes = K.slot_elems * 8;
+    __amdgpu_buffer_rsrc_t slr =
+        make_rsrc(reinterpret_cast<T *>(K.slots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
+    __amdgpu_buffer_rsrc_t sly =
+        make_rsrc(reinterpret_cast<T *>(K.wslots) + (long long)blockIdx.x * K.slot_elems, slot_bytes);
+    double *ubuf = reinterpret_cast<double *>(K.xslots) + (long long)blockIdx.x * K.slot_elems;
+    const __amdgpu_buffer_rsrc_t ulr = make_rsrc(ubuf, slot_bytes);
+    unsigned voff[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) voff[r] = cl.valid(r) ? (unsigned)cl.col[r] * 8u : kIdleOffset;
+
+    WorkSource work;
+    SnapPtr Ap;
+    long long qfirst, qend, qstep;
+    while (work.next(K, L, tid, Ap, qfirst, qend, qstep)) {
+    const auto &A = *Ap;
+    const int n = A.n;
+    const int npl = A.npl;
+    const __amdgpu_buffer_rsrc_t vr = make_rsrc(A.veff, A.nd * 8);
+    const __amdgpu_buffer_rsrc_t pvr = make_rsrc(A.pvals, A.pvals_bytes);
+    const double kin0 = -3.0 * A.w[0];
+
+    for (long long q = qfirst; q < qend; q += qstep) {
+        int qi, qj, qk;
+        node_coords(q, n, qi, qj, qk);
+        setup_region(A, L, qi, qj, qk, tid);
+        if (forces_centre_images(A, L, FL, tid) == 0) continue;
+        const int ni = L.ni < kMaxImages ? L.ni : kMaxImages;
+        const int nch = L.nch;
+        const unsigned zbase = (unsigned)pmod(qk - A.m, n);
+        const double chi = uniform(A.chi[q]), zeta = uniform(A.zeta[q]);
+        const double invz = uniform(1.0 / zeta);
+        forces_coefficients<C>(A, FL, chi, zeta, tid);
+        double kw[NO + 1];
+        kw[0] = 0.0;
+#pragma unroll
+        for (int d = 1; d <= NO; ++d) kw[d] = uniform(-0.5 * A.w[d] * invz);
+        const double c0 = uniform(kin0 - chi);
+        unsigned vcol[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            vcol[r] = cl.valid(r) ? (unsigned)(pmod(qi - A.m + cl.x, n) + n * pmod(qj - A.m + cl.y0 + r, n)) * 8u
+                                  : kIdleOffset;
+        T tv[RB][C];  // a window of planes of t^k
+        int cur = 0;
+        // t^0 goes to X here, so that every sweep reads X
+        projector_dots<false>(L, pvr, cl, cur, nch, [&](int r, int z) {
+            const T v = (centre_r == r && z == MC) ? 1.0 : 0.0;
+            bstore(v, slr, voff[r], (unsigned)(z * S::CC) * 8u);
+            return v;
+        });
+
+        for (int k = 0; k < npl; ++k) {
+            const double al = k == 0 ? 1.0 : 2.0;
+            const double scale = uniform(al * invz);
+            const double ua = uniform(k == 0 ? FL.cj[0] : 0.0), uc = uniform(FL.cj[k + 1]);
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK)
+                L.cs[i] = i < ni ? scale * L.img_coef[i] * L.s[cur][i] : 0.0;
+            Chain ch[RB][NCH];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) chains_start(L, pvr, Cols<C>::column(r), ch[r], nch);
+            double *snext = L.s[cur ^ 1];
+            unsigned zb = (unsigned)__builtin_amdgcn_readfirstlane((int)zbase);
+            asm volatile("" : "+s"(zb));
+            const bool prev = k > 0;
+#pragma unroll
+            for (int z = 0; z < (ZA < C ? ZA : C); ++z)
+#pragma unroll
+                for (int r = 0; r < RB; ++r) tv[r][z] = bload<T>(slr, voff[r], (unsigned)(z * S::CC) * 8u);
+            double vzn[RB], tpn[RB], upn[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                vzn[r] = bload<T>(vr, vcol[r], (unsigned)(n * n) * (zb % (unsigned)n) * 8u);
+                tpn[r] = 0.0;
+                upn[r] = 0.0;
+                if (prev) {
+                    tpn[r] = bload<T>(sly, voff[r], 0u);
+                    upn[r] = bload<T>(ulr, voff[r], 0u);
                 }
-                g3[0] += p * gx;
-                g3[1] += p * gy;
-                g3[2] += p * gz;
             }
-            atomicAdd(&FL.fs[m][0], g3[0]);
-            atomicAdd(&FL.fs[m][1], g3[1]);
-            atomicAdd(&FL.fs[m][2], g3[2]);
+#pragma unroll
+            for (int z = 0; z < C; ++z) {
+                const unsigned sz = (unsigned)(z * S::CC) * 8u;
+                double vz[RB], tprev[RB], uprev[RB];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    vz[r] = vzn[r];
+                    tprev[r] = tpn[r];
+                    uprev[r] = upn[r];
+                    if (z + 1 < C) {
+                        const unsigned sz1 = (unsigned)((z + 1) * S::CC) * 8u;
+                        const unsigned vz1 = (unsigned)(n * n) * ((zb + (unsigned)(z + 1)) % (unsigned)n) * 8u;
+                        vzn[r] = bload<T>(vr, vcol[r], vz1);
+                        if (prev) {
+                            tpn[r] = bload<T>(sly, voff[r], sz1);
+                            upn[r] = bload<T>(ulr, voff[r], sz1);
+                        }
+                    }
+                    if (z + ZA < C) tv[r][z + ZA] = bload<T>(slr, voff[r], (unsigned)((z + ZA) * S::CC) * 8u);
+                    L.plane[z & 1][cl.pcw[r]] = tv[r][z];
+                }
+                __syncthreads();
+                const PlaneView<C, T> pv(L.plane[0], z & 1, cl.corner);
+                T yrow[2 * NO + RB];
+                load_yrows<C, T>(pv, tv, z, yrow);
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const double acc = stencil_sum<C, T>(pv, yrow, tv[r], r, z, kw);
+                    const double tz = tv[r][z];
+                    const double u = acc + (vz[r] + c0) * invz * tz;
+                    double pval[NCH];
+                    double nvd = al * u - tprev[r];
+#pragma unroll
+                    for (int ci = 0; ci < NCH; ++ci) {
+                        pval[ci] = 0.0;
+                        if (ci == 0 || ci < nch) {
+                            pval[ci] = ch[r][ci].pv;
+                            nvd += L.cs[ch[r][ci].sl()] * pval[ci];
+                        }
+                    }
+                    if (!cl.valid(r)) nvd = 0.0;
+                    bstore(nvd, sly, voff[r], sz);                            // t^{k+1} over t^{k-1}
+                    bstore(ua * tz + uprev[r] + uc * nvd, ulr, voff[r], sz);  // u
+#pragma unroll
+                    for (int ci = 0; ci < NCH; ++ci) {
+                        if (ci == 0 || ci < nch) {
+                            ch[r][ci].acc += pval[ci] * nvd;
+                            pin(ch[r][ci].acc);
+                        }
+                    }
+                    chains_advance<C, NCH>(ch[r], snext, L.runs, pvr, z, nch);
+                }
+            }
+            __syncthreads();
+            {
+                // t^k -> t^{k-1}, t^{k+1} -> t^k: X and Y swap
+                const __amdgpu_buffer_rsrc_t t = slr;
+                slr = sly;
+                sly = t;
+            }
+            for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) L.s[cur][i] = 0.0;
+            cur ^= 1;
+            __syncthreads();
         }
-        __syncthreads();
-        if (tid < 3 * ncent) {
-            const int m = tid / 3, ax = tid % 3, I = FL.img[m];
-            atomicAdd(&A.forces[3 * L.img_atom[I] + ax], -4.0 * L.img_coef[I] * FL.pc[m] * FL.fs[m][ax]);
-        }
-        __syncthreads();
+        forces_gradient(A, L, FL, ubuf, tid);
     }
     }
 }
@@ -2852,7 +3047,11 @@ hipError_t launch_forces_t(const LaunchArgs &a, int nch, int nwg, hipStream_t s)
             return hipGetLastError();
         });
     } else {
-        return hipErrorInvalidValue;  // forces: resident cubes only
+        return with_chains<c>(nch, [&](auto ncht) {
+            constexpr int NCH = decltype(ncht)::value;
+            hipLaunchKernelGGL((forces_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            return hipGetLastError();
+        });
     }
 }
 template <int c>
