@@ -439,7 +439,7 @@ def main():
     reuse_s = reuse_pass(g, bounds, wl.n_electrons)
     log(f"pass reusing bounds: {reuse_s:.2f} s")
     forces = None
-    if C <= 31 and wl.npl <= 256:
+    if wl.npl <= 256:
         forces = forces_leg(g, wl, mu)
         log(f"nonlocal forces: {forces['seconds']:.2f} s over {forces['nodes']} nodes")
 
