@@ -245,6 +245,8 @@ def run_ensemble(args):
     t0 = time.perf_counter()
     tiles = b.autotune(cache)
     tune_s = time.perf_counter() - t0
+    # kernel shape bits per launch group (1: two rows per thread, 2: two planes per barrier)
+    tiles["shapes"] = [list(g) for g in b.groups()]
     log(f"ensemble: tiles {tiles} ({tune_s:.1f} s)")
     for _ in range(args.warmup):
         b.step()
@@ -266,7 +268,7 @@ def run_ensemble(args):
     del br
     log(f"ensemble: pass reusing bounds {reuse_s:.2f} s")
     # the same pass with the default tiles (32 nodes per item, occupancy-limited
-    # workgroups per CU), for the autotuner's gain
+    # workgroups per CU, default kernel shapes), for the autotuner's gain
     bd = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=True)
     bd.step()
     torch.cuda.synchronize()
@@ -275,6 +277,7 @@ def run_ensemble(args):
     torch.cuda.synchronize()
     default_s = time.perf_counter() - t1
     default_tiles = bd.tiles()
+    default_tiles["shapes"] = [list(g) for g in bd.groups()]
     del bd
     log(f"ensemble: default tiles {default_tiles}: {default_s:.2f} s per pass")
     node_steps = sum(g.nd * (wl.npl // 2) for g, wl in zip(snaps, wls))

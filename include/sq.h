@@ -220,7 +220,16 @@ typedef struct sq_batch_options {
                             bounds.  That test only catches escapes the moments
                             amplify past 1, which at low n_pl a moderate escape
                             need not do. */
+    int shape;           /* SQ_SHAPE_* bits for the recurrence launches of every cube
+                            side that has them (other sides ignore them); 0 (default):
+                            one cube column per thread and one plane per barrier.
+                            sq_batch_autotune chooses them per launch group. */
 } sq_batch_options;
+
+/* Kernel shapes of the batched recurrence launches (bits of sq_batch_options.shape). */
+#define SQ_SHAPE_TWO_ROWS 1   /* two y-adjacent cube columns per thread: 21-27-point cubes */
+#define SQ_SHAPE_TWO_PLANES 2 /* two cube planes per workgroup barrier in the FP64 Lanczos
+                                 and moments sweeps: 21-31-point cubes */
 
 void sq_batch_default_options(sq_batch_options *opt);
 
@@ -250,14 +259,22 @@ int sq_batch_step(sq_batch *batch, double *mu, double *energies, void *stream);
 
 /* Time the candidate tile shapes (block_nodes x wg_per_cu) on a sample of
  * every snapshot's nodes (the first eighth; Lanczos and moments launches
- * together) and keep the fastest; with cache_path (host, may be
- * NULL) the choice is read from / appended to that JSON file, keyed by the
- * device and the batch's cube sizes and precision.  Invalidates a captured
+ * together) and keep the fastest; then, at that tile, time every kernel shape
+ * (SQ_SHAPE_* combinations) each launch group's cube side has, that group
+ * alone, and keep its fastest.  With cache_path (host, may be NULL) the
+ * choice is read from / appended to that JSON file, keyed by the device and
+ * the batch's cube sizes, chain counts and precision.  Invalidates a captured
  * graph.  Synchronises `stream`. */
 int sq_batch_autotune(sq_batch *batch, const char *cache_path, void *stream);
 
 /* Chosen tile shape and the number of work items of the current queues. */
 int sq_batch_tiles(const sq_batch *batch, int *block_nodes, int *wg_per_cu, int *n_items);
+
+/* Launch group i of the batch (one per cube side and chain count, 0 <= i <
+ * *n_groups): its cube side, projector chains and SQ_SHAPE_* bits.  Any
+ * output may be NULL; SQ_EINVAL if i is out of range (n_groups is still
+ * written). */
+int sq_batch_group(const sq_batch *batch, int i, int *cube, int *nch, int *shape, int *n_groups);
 
 /* Release host state and the private stream and graph. */
 void sq_batch_destroy(sq_batch *batch);

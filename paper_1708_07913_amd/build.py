@@ -38,7 +38,10 @@ CXX = os.environ.get("CXX", "g++")
 
 # recurrence kernels are split into several translation units by cube size so
 # that the build parallelises
-CUBE_GROUPS = [[3, 5, 7, 9, 11, 13], [15, 17, 19], [21, 23], [25, 27], [29], [31], [33], [35], [37]]
+CUBE_GROUPS = [[3, 5, 7, 9, 11, 13], [15, 17, 19], [21], [23], [25], [27], [29], [31], [33], [35], [37]]
+# the two-row shapes of the 21-27-point cubes: a second build of the same
+# source (SQ_TWO_ROWS=1, kernels in namespace sq::two_rows)
+TWO_ROW_GROUPS = [[21], [23], [25], [27]]
 
 
 def _run(cmd):
@@ -55,10 +58,11 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     cmds = []
     objs = []
     src_k = os.path.join(CSRC, "sq_kernels.hip")
-    for i, group in enumerate(CUBE_GROUPS):
+    parts = [(g, 0) for g in CUBE_GROUPS] + [(g, 1) for g in TWO_ROW_GROUPS]
+    for i, (group, two) in enumerate(parts):
         cubes = " ".join(f"X({c})" for c in group)
         obj = os.path.join(BUILD, f"sq_kernels_{i}.o")
-        defs = [f"-DSQ_CUBES={cubes}", "-DSQ_PART=%d" % i]
+        defs = [f"-DSQ_CUBES={cubes}", "-DSQ_PART=%d" % i, "-DSQ_TWO_ROWS=%d" % two]
         cmds.append([HIPCC, *DEVICE_FLAGS, *defs, "-c", src_k, "-o", obj])
         objs.append(obj)
     obj = os.path.join(BUILD, "sq_common.o")

@@ -377,12 +377,22 @@ int guarded(F f) {
 // ---------------------------------------------------------------------------
 // Batched snapshots
 // ---------------------------------------------------------------------------
+static_assert(SQ_SHAPE_TWO_ROWS == sq::kShapeTwoRows && SQ_SHAPE_TWO_PLANES == sq::kShapeTwoPlanes,
+              "public and internal kernel shape bits");
+
 struct sq_batch {
     struct Group {
         int C = 0, nch = 2;
         std::vector<int> snaps;
-        int occ_l = 1, occ_m = 1;   // resident workgroups per CU (Lanczos, moments)
+        int shape = 0;              // kernel shape bits (sq::kShape*) of this group's launches
+        int occ_l = 1, occ_m = 1;   // resident workgroups per CU (Lanczos, moments) at that shape
+        int occ_lv[4] = {0, 0, 0, 0}, occ_mv[4] = {0, 0, 0, 0};  // the same for every shape the cube has
         int item0 = 0, n_items = 0; // range in the item table
+        void set_shape(int sh) {
+            shape = sh;
+            occ_l = occ_lv[sh];
+            occ_m = occ_mv[sh];
+        }
     };
     std::vector<sq_ctx *> ctx;
     std::vector<double *> moments, rho;
@@ -392,7 +402,7 @@ struct sq_batch {
     int device = 0, cus = 0, max_brent = 200;
     char device_name[256] = {0};
     std::vector<Group> groups;
-    long long max_slot = 0;          // largest workgroup slot (doubles) of any snapshot
+    long long max_slot = 0;          // largest workgroup slot (doubles) of any snapshot and shape
     int nwg_cap = 0;                 // largest grid of any launch (buffers are sized for it)
     int block_nodes = 32, wg_per_cu = 0;
     std::vector<sq::WorkItem> items;
@@ -505,7 +515,8 @@ sq::LaunchArgs group_launch(sq_batch *b, const sq_batch::Group &g, int counter) 
     return k;
 }
 
-int enqueue_recurrences(sq_batch *b, bool lanczos, bool moments, hipStream_t s) {
+// only >= 0: launch that group alone (the autotuner's per-group timing)
+int enqueue_recurrences(sq_batch *b, bool lanczos, bool moments, hipStream_t s, int only = -1) {
     const int ng = int(b->groups.size());
     int rc = hip_check(sq::launch_zero_ints(b->at<int>(b->off_counters), 2 * ng, s), "clearing work queues");
     if (rc) return rc;
@@ -515,16 +526,17 @@ int enqueue_recurrences(sq_batch *b, bool lanczos, bool moments, hipStream_t s) 
     }
     for (int gi = 0; lanczos && gi < ng; ++gi) {
         const auto &g = b->groups[size_t(gi)];
-        if (g.n_items == 0) continue;
-        rc = hip_check(sq::launch_lanczos(group_launch(b, g, 2 * gi), g.C, g.nch, batch_grid(b, g, true), s),
-                       "launching batched Lanczos");
+        if (g.n_items == 0 || (only >= 0 && gi != only)) continue;
+        rc = hip_check(
+            sq::launch_lanczos(group_launch(b, g, 2 * gi), g.C, g.nch, batch_grid(b, g, true), s, g.shape),
+            "launching batched Lanczos");
         if (rc) return rc;
     }
     for (int gi = 0; moments && gi < ng; ++gi) {
         const auto &g = b->groups[size_t(gi)];
-        if (g.n_items == 0) continue;
+        if (g.n_items == 0 || (only >= 0 && gi != only)) continue;
         rc = hip_check(sq::launch_moments(group_launch(b, g, 2 * gi + 1), g.C, g.nch, b->mixed,
-                                          batch_grid(b, g, false), s),
+                                          batch_grid(b, g, false), s, g.shape),
                        "launching batched moments");
         if (rc) return rc;
     }
@@ -717,7 +729,8 @@ int batch_layout(sq_batch *b) {
     return SQ_OK;
 }
 
-// Autotuner cache: a flat JSON object {"key": {"block_nodes": B, "wg_per_cu": W, "ms": T}, ...}.
+// Autotuner cache: a flat JSON object
+// {"key": {"block_nodes": B, "wg_per_cu": W, "shapes": [[C, nch, bits], ...], "ms": T}, ...}.
 std::string tune_key(const sq_batch *b) {
     std::vector<std::string> parts;
     for (const auto &g : b->groups) {
@@ -726,13 +739,17 @@ std::string tune_key(const sq_batch *b) {
         parts.push_back("C" + std::to_string(g.C) + "x" + std::to_string(g.nch) + ":" + std::to_string(nodes));
     }
     std::sort(parts.begin(), parts.end());
-    // "lm": timed on the Lanczos and moments launches together
-    std::string key = std::string(b->device_name) + "/" + std::to_string(b->cus) + "cu/lm/" + (b->mixed ? "mixed" : "fp64");
+    // "lms": timed on the Lanczos and moments launches together, with kernel shapes
+    std::string key = std::string(b->device_name) + "/" + std::to_string(b->cus) + "cu/lms/" + (b->mixed ? "mixed" : "fp64");
     for (const auto &p : parts) key += "/" + p;
     return key;
 }
 
-bool cache_lookup(const char *path, const std::string &key, int *block, int *wg) {
+struct TunedShape {
+    int C, nch, shape;
+};
+
+bool cache_lookup(const char *path, const std::string &key, int *block, int *wg, std::vector<TunedShape> *shapes) {
     if (!path) return false;
     FILE *f = std::fopen(path, "rb");
     if (!f) return false;
@@ -744,11 +761,28 @@ bool cache_lookup(const char *path, const std::string &key, int *block, int *wg)
     const size_t at = text.find("\"" + key + "\"");
     if (at == std::string::npos) return false;
     const size_t pb = text.find("\"block_nodes\":", at), pw = text.find("\"wg_per_cu\":", at);
-    if (pb == std::string::npos || pw == std::string::npos) return false;
-    return std::sscanf(text.c_str() + pb + 14, "%d", block) == 1 && std::sscanf(text.c_str() + pw + 12, "%d", wg) == 1;
+    const size_t ps = text.find("\"shapes\":", at);
+    if (pb == std::string::npos || pw == std::string::npos || ps == std::string::npos) return false;
+    if (std::sscanf(text.c_str() + pb + 14, "%d", block) != 1 || std::sscanf(text.c_str() + pw + 12, "%d", wg) != 1)
+        return false;
+    size_t i = text.find('[', ps);
+    if (i == std::string::npos) return false;
+    shapes->clear();
+    for (++i;;) {
+        while (i < text.size() && (text[i] == ' ' || text[i] == ',' || text[i] == '\n')) ++i;
+        if (i >= text.size()) return false;
+        if (text[i] == ']') return true;
+        TunedShape t{};
+        if (text[i] != '[' || std::sscanf(text.c_str() + i, "[%d, %d, %d]", &t.C, &t.nch, &t.shape) != 3) return false;
+        shapes->push_back(t);
+        i = text.find(']', i);
+        if (i == std::string::npos) return false;
+        ++i;
+    }
 }
 
-void cache_store(const char *path, const std::string &key, int block, int wg, double ms) {
+void cache_store(const char *path, const std::string &key, int block, int wg, const std::vector<TunedShape> &shapes,
+                 double ms) {
     if (!path) return;
     std::string text;
     if (FILE *f = std::fopen(path, "rb")) {
@@ -758,12 +792,19 @@ void cache_store(const char *path, const std::string &key, int block, int wg, do
         std::fclose(f);
     }
     const size_t close = text.rfind('}');
-    char entry[512];
-    std::snprintf(entry, sizeof(entry), "\"%s\": {\"block_nodes\": %d, \"wg_per_cu\": %d, \"ms\": %.3f}", key.c_str(),
-                  block, wg, ms);
+    std::string sh = "[";
+    for (size_t i = 0; i < shapes.size(); ++i)
+        sh += (i ? ", [" : "[") + std::to_string(shapes[i].C) + ", " + std::to_string(shapes[i].nch) + ", " +
+              std::to_string(shapes[i].shape) + "]";
+    sh += "]";
+    char fields[128];
+    std::snprintf(fields, sizeof(fields), "\": {\"block_nodes\": %d, \"wg_per_cu\": %d, \"shapes\": ", block, wg);
+    char ms_field[64];
+    std::snprintf(ms_field, sizeof(ms_field), ", \"ms\": %.3f}", ms);
+    const std::string entry = "\"" + key + fields + sh + ms_field;
     std::string out;
     if (close == std::string::npos || text.find('{') == std::string::npos) {
-        out = std::string("{\n ") + entry + "\n}\n";
+        out = "{\n " + entry + "\n}\n";
     } else {
         std::string head = text.substr(0, close);
         while (!head.empty() && (head.back() == '\n' || head.back() == ' ')) head.pop_back();
@@ -1151,6 +1192,7 @@ void sq_batch_default_options(sq_batch_options *opt) {
     opt->use_graph = 1;
     opt->bounds_every = 1;
     opt->reuse_check = 1;
+    opt->shape = 0;
 }
 
 int sq_batch_create(sq_batch **out, sq_ctx *const *ctxs, int n, double *const *moments, double *const *rho,
@@ -1166,6 +1208,7 @@ int sq_batch_create(sq_batch **out, sq_ctx *const *ctxs, int n, double *const *m
         if (b->opt.block_nodes < 0 || b->opt.wg_per_cu < 0 || b->opt.bounds_every < 0)
             return fail(SQ_EINVAL, "invalid batch options");
         if (b->opt.block_nodes > 0 && b->opt.block_nodes < 8) return fail(SQ_EINVAL, "block_nodes must be 0 or >= 8");
+        if (b->opt.shape & ~(SQ_SHAPE_TWO_ROWS | SQ_SHAPE_TWO_PLANES)) return fail(SQ_EINVAL, "unknown shape bits");
         for (int i = 0; i < n; ++i) {
             sq_ctx *c = ctxs[i];
             int rc = check_ctx(c, kBound);
@@ -1183,7 +1226,8 @@ int sq_batch_create(sq_batch **out, sq_ctx *const *ctxs, int n, double *const *m
             b->rho.push_back(rho[i]);
             b->n_e.push_back(n_electrons[i]);
             b->max_brent = i == 0 ? c->opt.max_brent : std::max(b->max_brent, c->opt.max_brent);
-            b->max_slot = std::max(b->max_slot, sq::slot_elems_for(c->C));
+            // slots hold the layout of any shape the autotuner may pick
+            b->max_slot = std::max({b->max_slot, sq::slot_elems_for(c->C, 0), sq::slot_elems_for(c->C, 1)});
             // one launch per cube side and chain count
             auto g = std::find_if(b->groups.begin(), b->groups.end(),
                                   [&](const sq_batch::Group &x) { return x.C == c->C && x.nch == c->nch; });
@@ -1205,11 +1249,21 @@ int sq_batch_create(sq_batch **out, sq_ctx *const *ctxs, int n, double *const *m
         if (rc) return rc;
         std::snprintf(b->device_name, sizeof(b->device_name), "%s", prop.gcnArchName);
         for (auto &g : b->groups) {
-            rc = hip_check(sq::recurrence_occupancy(g.C, true, false, g.nch, &g.occ_l), "occupancy (Lanczos)");
-            if (!rc) rc = hip_check(sq::recurrence_occupancy(g.C, false, b->mixed, g.nch, &g.occ_m), "occupancy (moments)");
-            if (rc) return rc;
-            if (g.occ_l < 1 || g.occ_m < 1) return fail(SQ_EDEVICE, "recurrence kernel does not fit on a compute unit");
-            b->nwg_cap = std::max({b->nwg_cap, b->cus * g.occ_l, b->cus * g.occ_m});
+            // every shape of the cube side (buffers are sized for the widest grid)
+            const int variants = sq::shape_variants(g.C);
+            for (int sh = 0; sh < 4; ++sh) {
+                if (sh & ~variants) continue;
+                rc = hip_check(sq::recurrence_occupancy(g.C, true, false, g.nch, &g.occ_lv[sh], sh),
+                               "occupancy (Lanczos)");
+                if (!rc)
+                    rc = hip_check(sq::recurrence_occupancy(g.C, false, b->mixed, g.nch, &g.occ_mv[sh], sh),
+                                   "occupancy (moments)");
+                if (rc) return rc;
+                if (g.occ_lv[sh] < 1 || g.occ_mv[sh] < 1)
+                    return fail(SQ_EDEVICE, "recurrence kernel does not fit on a compute unit");
+                b->nwg_cap = std::max({b->nwg_cap, b->cus * g.occ_lv[sh], b->cus * g.occ_mv[sh]});
+            }
+            g.set_shape(b->opt.shape & variants);
         }
         b->block_nodes = b->opt.block_nodes > 0 ? b->opt.block_nodes : 32;
         b->wg_per_cu = b->opt.wg_per_cu;
@@ -1366,9 +1420,12 @@ int sq_batch_autotune(sq_batch *b, const char *cache_path, void *stream) {
         b->have_bounds = false;  // the tuning runs rewrite chi and zeta
         const std::string key = tune_key(b);
         int best_block = 0, best_wg = 0;
-        if (!cache_lookup(cache_path, key, &best_block, &best_wg)) {
+        std::vector<TunedShape> shapes;
+        if (!cache_lookup(cache_path, key, &best_block, &best_wg, &shapes)) {
+            shapes.clear();
             rc = upload_args(b, b->own);
             if (rc) return rc;
+            for (auto &g : b->groups) g.set_shape(0);
             int max_occ = 1;
             for (const auto &g : b->groups) max_occ = std::max({max_occ, g.occ_l, g.occ_m});
             std::vector<int> wgs = {1};
@@ -1377,21 +1434,26 @@ int sq_batch_autotune(sq_batch *b, const char *cache_path, void *stream) {
             rc = hip_check(hipEventCreate(&e0), "autotune events");
             if (!rc) rc = hip_check(hipEventCreate(&e1), "autotune events");
             if (rc) return rc;
+            // one timed pass of the sample (only >= 0: that launch group alone)
+            auto timed = [&](int only, float *ms) -> int {
+                int r = hip_check(hipEventRecord(e0, b->own), "autotune timing");
+                if (!r) r = enqueue_recurrences(b, true, true, b->own, only);
+                if (!r) r = hip_check(hipEventRecord(e1, b->own), "autotune timing");
+                if (!r) r = hip_check(hipEventSynchronize(e1), "autotune timing");
+                if (!r) r = hip_check(hipEventElapsedTime(ms, e0, e1), "autotune timing");
+                return r;
+            };
             double best_ms = 1e300;
             // a sample of every snapshot (its first 1/8 of the nodes) through
             // both recurrence kernels: Lanczos (which also gives the sample's
-            // bounds) and the moments
+            // bounds) and the moments, at the default kernel shapes
             for (int block : {8, 32, 128}) {
                 for (int wg : wgs) {
                     build_items(b, block, 0.125);
                     b->wg_per_cu = wg;
                     rc = upload_items(b, b->own);
-                    if (!rc) rc = hip_check(hipEventRecord(e0, b->own), "autotune timing");
-                    if (!rc) rc = enqueue_recurrences(b, true, true, b->own);
-                    if (!rc) rc = hip_check(hipEventRecord(e1, b->own), "autotune timing");
-                    if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune timing");
                     float ms = 0.f;
-                    if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing");
+                    if (!rc) rc = timed(-1, &ms);
                     if (rc) break;
                     if (ms < best_ms) {
                         best_ms = ms;
@@ -1401,10 +1463,45 @@ int sq_batch_autotune(sq_batch *b, const char *cache_path, void *stream) {
                 }
                 if (rc) break;
             }
+            // then, at that tile, every kernel shape of each group's cube side,
+            // the group alone (best of two runs: the first launch of a shape
+            // may also load its code object)
+            if (!rc) {
+                build_items(b, best_block, 0.125);
+                b->wg_per_cu = best_wg;
+                rc = upload_items(b, b->own);
+            }
+            for (int gi = 0; !rc && gi < int(b->groups.size()); ++gi) {
+                auto &g = b->groups[size_t(gi)];
+                const int variants = sq::shape_variants(g.C);
+                if (variants == 0 || g.n_items == 0) continue;
+                int best_sh = 0;
+                double best_g = 1e300;
+                for (int sh = 0; sh < 4 && !rc; ++sh) {
+                    if (sh & ~variants) continue;
+                    g.set_shape(sh);
+                    float ms = 0.f, ms2 = 0.f;
+                    rc = timed(gi, &ms);
+                    if (!rc) rc = timed(gi, &ms2);
+                    if (!rc && std::min(ms, ms2) < best_g) {
+                        best_g = std::min(ms, ms2);
+                        best_sh = sh;
+                    }
+                }
+                g.set_shape(best_sh);
+                shapes.push_back({g.C, g.nch, best_sh});
+            }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             if (rc) return rc;
-            cache_store(cache_path, key, best_block, best_wg, best_ms);
+            cache_store(cache_path, key, best_block, best_wg, shapes, best_ms);
+        } else {
+            for (auto &g : b->groups) {
+                int sh = 0;
+                for (const auto &t : shapes)
+                    if (t.C == g.C && t.nch == g.nch) sh = t.shape & sq::shape_variants(g.C);
+                g.set_shape(sh);
+            }
         }
         b->block_nodes = best_block;
         b->wg_per_cu = best_wg;
@@ -1420,6 +1517,17 @@ int sq_batch_tiles(const sq_batch *b, int *block_nodes, int *wg_per_cu, int *n_i
     if (block_nodes) *block_nodes = b->block_nodes;
     if (wg_per_cu) *wg_per_cu = b->wg_per_cu;
     if (n_items) *n_items = int(b->items.size());
+    return SQ_OK;
+}
+
+int sq_batch_group(const sq_batch *b, int i, int *cube, int *nch, int *shape, int *n_groups) {
+    if (!b) return fail(SQ_EINVAL, "null batch");
+    if (n_groups) *n_groups = int(b->groups.size());
+    if (i < 0 || i >= int(b->groups.size())) return fail(SQ_EINVAL, "launch group index out of range");
+    const auto &g = b->groups[size_t(i)];
+    if (cube) *cube = g.C;
+    if (nch) *nch = g.nch;
+    if (shape) *shape = g.shape;
     return SQ_OK;
 }
 

@@ -18,12 +18,18 @@ constexpr int kResidentCube = 31; // largest cube side whose columns stay in reg
 // up to 27 points (a workgroup of C^2 threads, 7-12 waves for 21-27 points),
 // two y-adjacent columns for 29 and 31 points (512-thread workgroups, 256
 // VGPRs per lane; the pair shares its y-neighbour reads), three beyond 31
-// points.  Two rows on the 21-27-point cubes leave one wave per SIMD and run
-// 12-31 % slower; one row on 29 points spills.
-constexpr int rows_per_thread(int C) { return C > kResidentCube ? 3 : (C >= 29 ? 2 : 1); }
-// Threads per row group (lanes along x): 29- and 31-point cubes give each row
-// group 32 lanes, the last ones idle.
-constexpr int row_group_threads(int C) { return (C == 29 || C == 31) ? 32 : C; }
+// points.  One row on 29 points spills.  The 21-27-point cubes also have a
+// two-row shape (`two` = 1: 32-lane row groups, 6-7 waves), built as a
+// separate set of kernels that batches may select (kShapeTwoRows).
+constexpr bool has_two_row_shape(int C) { return C >= 21 && C <= 27; }
+constexpr int rows_per_thread(int C, int two = 0) {
+    return C > kResidentCube ? 3 : (C >= 29 || (two && has_two_row_shape(C)) ? 2 : 1);
+}
+// Threads per row group (lanes along x): two-row shapes give each row group
+// 32 lanes, the last ones idle.
+constexpr int row_group_threads(int C, int two = 0) {
+    return (C == 29 || C == 31 || (two && has_two_row_shape(C))) ? 32 : C;
+}
 // Doubles per plane of a workgroup's recurrence slot.  The Lanczos ring
 // kernel (cubes up to kResidentCube) stores plane z of a vector thread by
 // thread: the thread at x in row group g keeps its rows r at elements
@@ -31,12 +37,24 @@ constexpr int row_group_threads(int C) { return (C == 29 || C == 31) ? 32 : C; }
 // one 8- or 16-byte access and a row group's stores are contiguous.  The
 // moments kernels and the streamed kernels store the cube's plane, element
 // z * C^2 + y * C + x, which fits as slot_plane >= C^2.
-constexpr long long slot_plane(int C) {
-    return C > kResidentCube
-               ? (long long)C * C
-               : (long long)((C + rows_per_thread(C) - 1) / rows_per_thread(C)) * C * rows_per_thread(C);
+constexpr long long slot_plane(int C, int two = 0) {
+    return C > kResidentCube ? (long long)C * C
+                             : (long long)((C + rows_per_thread(C, two) - 1) / rows_per_thread(C, two)) * C *
+                                   rows_per_thread(C, two);
 }
-constexpr long long slot_elems_for(int C) { return (long long)C * slot_plane(C); }
+constexpr long long slot_elems_for(int C, int two = 0) { return (long long)C * slot_plane(C, two); }
+
+// Kernel shape variants of the register-ring recurrence kernels (bit set):
+// two rows per thread (cubes with has_two_row_shape) and two planes per
+// barrier in the FP64 Lanczos and moments sweeps (ring cubes of 21 points
+// and more; four LDS plane buffers instead of two).
+constexpr int kShapeTwoRows = 1;
+constexpr int kShapeTwoPlanes = 2;
+constexpr bool has_two_plane_shape(int C) { return C >= 21 && C <= kResidentCube; }
+// Variants that exist for cube side C (a subset of the bits above).
+constexpr int shape_variants(int C) {
+    return (has_two_row_shape(C) ? kShapeTwoRows : 0) | (has_two_plane_shape(C) ? kShapeTwoPlanes : 0);
+}
 
 // One atom's projector, stored as z-runs: for every (dx, dy) column of the
 // sphere relative to the base node (bx, by, bz) = floor(R / h), the contiguous
@@ -264,13 +282,15 @@ struct FermiSnap {
 
 // Launchers (sq_kernels.hip).  Return hipSuccess or the launch error.
 // C is the cube side and nch the projector chains of every snapshot launched.
-hipError_t launch_lanczos(const LaunchArgs &k, int C, int nch, int nwg, hipStream_t s);
-hipError_t launch_moments(const LaunchArgs &k, int C, int nch, bool mixed, int nwg, hipStream_t s);
+// `shape`: kShape* bits (0 = the default shape); bits that cube side C does
+// not have return hipErrorInvalidValue.
+hipError_t launch_lanczos(const LaunchArgs &k, int C, int nch, int nwg, hipStream_t s, int shape = 0);
+hipError_t launch_moments(const LaunchArgs &k, int C, int nch, bool mixed, int nwg, hipStream_t s, int shape = 0);
 hipError_t launch_forces(const LaunchArgs &k, int C, int nch, int nwg, hipStream_t s);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
 hipError_t launch_zero_doubles(double *p, int n, hipStream_t s);
-int recurrence_block(int C);
-hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int nch, int *blocks_per_cu);
+int recurrence_block(int C, int shape = 0);
+hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int nch, int *blocks_per_cu, int shape = 0);
 hipError_t launch_set_bounds(const double *lmin, const double *lmax, double *chi, double *zeta,
                              long long nd, double margin, hipStream_t s);
 hipError_t launch_quadrature_weights(const double *mom, const double *ctab, double *W,

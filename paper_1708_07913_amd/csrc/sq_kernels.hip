@@ -31,6 +31,9 @@
 #include <type_traits>
 
 namespace sq {
+#if SQ_TWO_ROWS
+namespace two_rows {
+#endif
 namespace {
 
 constexpr int NO = kNoMax;
@@ -44,13 +47,14 @@ constexpr int NO = kNoMax;
 #ifndef SQ_LANCZOS_AHEAD
 #define SQ_LANCZOS_AHEAD 1
 #endif
-#ifndef SQ_RING_PPB
-#define SQ_RING_PPB 1
+// Two-row build of the 21-27-point cubes (a second object of this file; its
+// kernels live in namespace sq::two_rows)
+#ifndef SQ_TWO_ROWS
+#define SQ_TWO_ROWS 0
 #endif
 constexpr int kMomentsAhead = SQ_MOMENTS_AHEAD;
 // FP32-mixed moments: leading steps run in FP64 (see moments_mixed_kernel)
 constexpr int kMixedFp64Steps = 4;
-constexpr int kRingPlanesPerBarrier = SQ_RING_PPB;  // 1 or 2 (four plane buffers)
 constexpr int kLanczosAhead = SQ_LANCZOS_AHEAD;
 
 // Smallest row stride >= pe for which a step from (x = xw - 1, y) to
@@ -65,15 +69,15 @@ constexpr int plane_stride(int c, int rb, int xw, int pe) {
 
 template <int C>
 struct Shape {
-    static constexpr int RB = rows_per_thread(C);
+    static constexpr int RB = rows_per_thread(C, SQ_TWO_ROWS);
     static constexpr int CC = C * C;
     static constexpr int YP = (C + RB - 1) / RB;            // row groups
     // 29- and 31-point cubes give each row group 32 lanes (the last idle or
     // two): a half-wave then reads 32 consecutive plane entries, which keeps
     // the 64-bit LDS reads free of bank conflicts
-    static constexpr int XW = row_group_threads(C);         // threads per row group
+    static constexpr int XW = row_group_threads(C, SQ_TWO_ROWS);  // threads per row group
     static constexpr int NT = XW * YP;                       // threads owning row groups
-    static constexpr int SP = (int)slot_plane(C);            // doubles per slot plane
+    static constexpr int SP = (int)slot_plane(C, SQ_TWO_ROWS);  // doubles per slot plane
     static constexpr int PE = C + 2 * NO;                    // padded plane edge (zero halo NO)
     // Row stride of the plane.  With XW = C the lanes of a wave run along x
     // and step to the next row group at x = C; a stride with
@@ -94,8 +98,8 @@ struct Shape {
     // 2 NO + 2 planes in registers
     static constexpr bool STREAM = C > kResidentCube;
     // plane buffers: two for the streamed kernels (one plane per barrier);
-    // four for the register-ring kernels, which use two, or all four when
-    // built with two planes per barrier (SQ_RING_PPB=2)
+    // four for the register-ring kernels, which use two, or all four with
+    // two planes per barrier
     static constexpr int NBUF = STREAM ? 2 : 4;
     static constexpr int CPT = (CC + BLOCK - 1) / BLOCK;     // columns per thread in the set-up scan
 };
@@ -1506,7 +1510,7 @@ struct MomentsStep {
 
 // FORCE: instead of the moments, accumulate u = sum_j c_j t^j in the vector
 // buffer `ur` (same layout as the slot; read and rewritten plane by plane).
-template <int C, int NCH, bool UP, bool FORCE = false, typename AT>
+template <int C, int NCH, bool UP, int PPB, bool FORCE = false, typename AT>
 __device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, NCH> &L, const Cols<C> &cl,
                                                    double (&R)[Shape<C>::RB][C + NO + 1],
                                                    __amdgpu_buffer_rsrc_t slr, __amdgpu_buffer_rsrc_t vr,
@@ -1529,7 +1533,7 @@ __device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, N
     // V_eff runs PPB planes ahead and t^{k-1} TPA planes ahead.  At k = 0 the
     // t^{k-1} loads use the idle offset (they read 0) instead of a branch,
     // which would serialise the prefetch.
-    constexpr int PPB = kRingPlanesPerBarrier;
+    static_assert(PPB == 1 || PPB == 2, "one or two planes per barrier");
     constexpr int TPA = kMomentsAhead > PPB ? kMomentsAhead : PPB;
     unsigned poff[RB];
 #pragma unroll
@@ -1636,7 +1640,8 @@ __device__ __forceinline__ void moments_ring_sweep(const AT &A, Lds<C, double, N
     __syncthreads();
 }
 
-template <int C, int NCH>
+// PPB: planes per barrier of the sweeps (1 or 2).
+template <int C, int NCH, int PPB>
 __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_ring_kernel(LaunchArgs K) {
     using S = Shape<C>;
     constexpr int RB = S::RB;
@@ -1717,7 +1722,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_ring_kernel(LaunchArg
             st.k = k;
             st.prev = k > 0;
             double d[2] = {0.0, 0.0};
-            moments_ring_sweep<C, NCH, UP>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st, L.s[cur ^ 1], nch,
+            moments_ring_sweep<C, NCH, UP, PPB>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st, L.s[cur ^ 1], nch,
                                            centre_r, mrow, d[0], d[1], slr);
             // the sweep ended on a barrier: the dots of t^{k+1} are complete.
             // Coefficients of the next step, and its dot accumulator cleared;
@@ -1948,7 +1953,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void forces_ring_kernel(LaunchArgs
             st.ua = uniform(k == 0 ? FL.cj[0] : 0.0);
             st.uc = uniform(FL.cj[k + 1]);
             double d[2] = {0.0, 0.0};
-            moments_ring_sweep<C, NCH, UP, true>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st, L.s[cur ^ 1],
+            moments_ring_sweep<C, NCH, UP, 1, true>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st, L.s[cur ^ 1],
                                                  nch, centre_r, nullptr, d[0], d[1], ulr);
             const double scale = uniform(2.0 * invz);
             for (int i = fresh_tid(); i < kMaxImages; i += S::BLOCK) {
@@ -2351,10 +2356,10 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void moments_mixed_kernel(LaunchAr
                     begin_step(k + h);
                     double d1 = 0.0, d2 = 0.0;
                     if (h == 0)
-                        moments_ring_sweep<C, NCH, true>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st,
+                        moments_ring_sweep<C, NCH, true, 1>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st,
                                                          L.s[cur ^ 1], nch, centre_r, mrow, d1, d2, slr);
                     else
-                        moments_ring_sweep<C, NCH, false>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st,
+                        moments_ring_sweep<C, NCH, false, 1>(A, L, cl, R, slr, vr, pvr, vcol, voff, zbase, kw, st,
                                                           L.s[cur ^ 1], nch, centre_r, mrow, d1, d2, slr);
                     end_step(k + h, d1, d2);
                 }
@@ -2414,7 +2419,7 @@ struct LanczosStep {
     bool ra, rb;        // x_{j-1} / x_{j-2} are read
 };
 
-template <int C, int NCH, bool UP, typename AT>
+template <int C, int NCH, bool UP, int PPB, typename AT>
 __device__ __forceinline__ void lanczos_ring_sweep(const AT &A, Lds<C, double, NCH> &L, const Cols<C> &cl,
                                                    double (&R)[Shape<C>::RB][C + NO + 1],
                                                    __amdgpu_buffer_rsrc_t rda, __amdgpu_buffer_rsrc_t rdb,
@@ -2492,7 +2497,7 @@ __device__ __forceinline__ void lanczos_ring_sweep(const AT &A, Lds<C, double, N
 #pragma unroll
     for (int f = 0; f < NO && f < C; ++f) form(f);
     // PPB planes share one barrier; V_eff runs PPB planes ahead
-    constexpr int PPB = kRingPlanesPerBarrier;
+    static_assert(PPB == 1 || PPB == 2, "one or two planes per barrier");
     double vzq[PPB][RB];
     auto vload = [&](int i, int r) {
         const int zz = D::plane(i, C);
@@ -2548,7 +2553,8 @@ __device__ __forceinline__ void lanczos_ring_sweep(const AT &A, Lds<C, double, N
     dots[2] = de;
 }
 
-template <int C, int NCH>
+// PPB: planes per barrier of the sweeps (1 or 2).
+template <int C, int NCH, int PPB>
 __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_ring_kernel(LaunchArgs K) {
     using S = Shape<C>;
     constexpr int RB = S::RB;
@@ -2629,7 +2635,7 @@ __global__ __launch_bounds__(Shape<C>::BLOCK) void lanczos_ring_kernel(LaunchArg
             const __amdgpu_buffer_rsrc_t rda = (j & 1) ? s0 : s1;  // x_{j-1}
             const __amdgpu_buffer_rsrc_t rdb = (j & 1) ? s1 : s0;  // x_{j-2}, then x_j
             double dots[4];
-            lanczos_ring_sweep<C, NCH, UP>(A, L, cl, R, rda, rdb, vr, pvr, vcol, cl.slot, zbase, kw, kin0, st,
+            lanczos_ring_sweep<C, NCH, UP, PPB>(A, L, cl, R, rda, rdb, vr, pvr, vcol, cl.slot, zbase, kw, kin0, st,
                                            L.s[cur ^ 1], nch, dots);
             // the sweep ended on a barrier: every run is closed.  sum_I c_I
             // s_I(x_j)^2, the next formation's coefficients c_I s_I(x_j) and a
@@ -3014,30 +3020,52 @@ hipError_t with_chains(int nch, F &&f) {
         return hipErrorInvalidValue;
     }
 }
-template <int c>
-hipError_t launch_lanczos_t(const LaunchArgs &a, int nch, int nwg, hipStream_t s) {
-    return with_chains<c>(nch, [&](auto ncht) {
-        constexpr int NCH = decltype(ncht)::value;
-        if constexpr (!Shape<c>::STREAM)
-            hipLaunchKernelGGL((lanczos_ring_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
-        else
-            hipLaunchKernelGGL((lanczos_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
-        return hipGetLastError();
-    });
+// Planes per barrier of the ring kernels for shape bits `shape`.
+template <int c, typename F>
+hipError_t with_planes(int shape, F &&f) {
+    if constexpr (has_two_plane_shape(c))
+        if (shape & kShapeTwoPlanes) return f(std::integral_constant<int, 2>());
+    return f(std::integral_constant<int, 1>());
 }
 template <int c>
-hipError_t launch_moments_t(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s) {
+hipError_t launch_lanczos_t(const LaunchArgs &a, int nch, int nwg, hipStream_t s, int shape) {
     return with_chains<c>(nch, [&](auto ncht) {
         constexpr int NCH = decltype(ncht)::value;
         if constexpr (!Shape<c>::STREAM) {
-            if (mixed) hipLaunchKernelGGL((moments_mixed_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
-            else hipLaunchKernelGGL((moments_ring_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            return with_planes<c>(shape, [&](auto ppbt) {
+                constexpr int PPB = decltype(ppbt)::value;
+                hipLaunchKernelGGL((lanczos_ring_kernel<c, NCH, PPB>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+                return hipGetLastError();
+            });
         } else {
-            hipLaunchKernelGGL((moments_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            hipLaunchKernelGGL((lanczos_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            return hipGetLastError();
         }
-        return hipGetLastError();
     });
 }
+// The FP32-mixed moments kernel has one plane per barrier (the two-plane bit
+// selects the FP64 moments sweep's variant only).
+template <int c>
+hipError_t launch_moments_t(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s, int shape) {
+    return with_chains<c>(nch, [&](auto ncht) {
+        constexpr int NCH = decltype(ncht)::value;
+        if constexpr (!Shape<c>::STREAM) {
+            if (mixed) {
+                hipLaunchKernelGGL((moments_mixed_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+                return hipGetLastError();
+            }
+            return with_planes<c>(shape, [&](auto ppbt) {
+                constexpr int PPB = decltype(ppbt)::value;
+                hipLaunchKernelGGL((moments_ring_kernel<c, NCH, PPB>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+                return hipGetLastError();
+            });
+        } else {
+            hipLaunchKernelGGL((moments_kernel<c, NCH>), dim3(nwg), dim3(Shape<c>::BLOCK), 0, s, a);
+            return hipGetLastError();
+        }
+    });
+}
+#if !SQ_TWO_ROWS
 template <int c>
 hipError_t launch_forces_t(const LaunchArgs &a, int nch, int nwg, hipStream_t s) {
     if constexpr (!Shape<c>::STREAM) {
@@ -3054,15 +3082,20 @@ hipError_t launch_forces_t(const LaunchArgs &a, int nch, int nwg, hipStream_t s)
         });
     }
 }
+#endif
 template <int c>
-hipError_t occupancy_t(bool lanczos, bool mixed, int nch, int *nb) {
+hipError_t occupancy_t(bool lanczos, bool mixed, int nch, int *nb, int shape) {
     const int B = Shape<c>::BLOCK;
     return with_chains<c>(nch, [&](auto ncht) {
         constexpr int NCH = decltype(ncht)::value;
         if constexpr (!Shape<c>::STREAM) {
-            if (lanczos) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_ring_kernel<c, NCH>, B, 0);
-            if (mixed) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_mixed_kernel<c, NCH>, B, 0);
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_ring_kernel<c, NCH>, B, 0);
+            if (!lanczos && mixed) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_mixed_kernel<c, NCH>, B, 0);
+            return with_planes<c>(shape, [&](auto ppbt) {
+                constexpr int PPB = decltype(ppbt)::value;
+                if (lanczos)
+                    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_ring_kernel<c, NCH, PPB>, B, 0);
+                return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_ring_kernel<c, NCH, PPB>, B, 0);
+            });
         } else {
             if (lanczos) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, lanczos_kernel<c, NCH>, B, 0);
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, moments_kernel<c, NCH>, B, 0);
@@ -3070,40 +3103,71 @@ hipError_t occupancy_t(bool lanczos, bool mixed, int nch, int *nb) {
     });
 }
 
-// Per-cube entry points of this translation unit (SQ_CUBES lists its cubes).
-#define X(c)                                                                                        \
-    hipError_t lanczos_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s) {                 \
-        return launch_lanczos_t<c>(a, nch, nwg, s);                                                 \
-    }                                                                                               \
-    hipError_t moments_c##c(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s) {     \
-        return launch_moments_t<c>(a, nch, mixed, nwg, s);                                          \
-    }                                                                                               \
-    hipError_t forces_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s) {                  \
-        return launch_forces_t<c>(a, nch, nwg, s);                                                  \
-    }                                                                                               \
-    hipError_t occupancy_c##c(bool lanczos, bool mixed, int nch, int *nb) {                         \
-        return occupancy_t<c>(lanczos, mixed, nch, nb);                                             \
-    }                                                                                               \
+// Per-cube entry points of this translation unit (SQ_CUBES lists its cubes;
+// the two-row build has no force kernels).
+#define X_RECURRENCE(c)                                                                                     \
+    hipError_t lanczos_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s, int shape) {              \
+        return launch_lanczos_t<c>(a, nch, nwg, s, shape);                                                  \
+    }                                                                                                       \
+    hipError_t moments_c##c(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s, int shape) { \
+        return launch_moments_t<c>(a, nch, mixed, nwg, s, shape);                                           \
+    }                                                                                                       \
+    hipError_t occupancy_c##c(bool lanczos, bool mixed, int nch, int *nb, int shape) {                      \
+        return occupancy_t<c>(lanczos, mixed, nch, nb, shape);                                              \
+    }                                                                                                       \
     int block_c##c() { return Shape<c>::BLOCK; }
+#if SQ_TWO_ROWS
+#define X(c) X_RECURRENCE(c)
+#else
+#define X(c)                                                                       \
+    X_RECURRENCE(c)                                                                \
+    hipError_t forces_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s) { \
+        return launch_forces_t<c>(a, nch, nwg, s);                                 \
+    }
+#endif
 #ifdef SQ_CUBES
 SQ_CUBES
 #else
 SQ_ALL_CUBES
 #endif
 #undef X
+#undef X_RECURRENCE
 #endif  // !SQ_COMMON_ONLY
 
+#if SQ_TWO_ROWS
+}  // namespace two_rows
+#endif
+
 #if defined(SQ_COMMON_ONLY) || !defined(SQ_CUBES)
-#define X(c)                                                                         \
-    hipError_t lanczos_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s);  \
-    hipError_t moments_c##c(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s); \
-    hipError_t forces_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s);   \
-    hipError_t occupancy_c##c(bool lanczos, bool mixed, int nch, int *nb);          \
+#define X_RECURRENCE_DECL(c)                                                                               \
+    hipError_t lanczos_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s, int shape);              \
+    hipError_t moments_c##c(const LaunchArgs &a, int nch, bool mixed, int nwg, hipStream_t s, int shape); \
+    hipError_t occupancy_c##c(bool lanczos, bool mixed, int nch, int *nb, int shape);                      \
     int block_c##c();
+#define X(c)          \
+    X_RECURRENCE_DECL(c) \
+    hipError_t forces_c##c(const LaunchArgs &a, int nch, int nwg, hipStream_t s);
 SQ_ALL_CUBES
 #undef X
+// cubes with a two-row build (has_two_row_shape)
+#define SQ_TWO_ROW_CUBES X(21) X(23) X(25) X(27)
+namespace two_rows {
+#define X(c) X_RECURRENCE_DECL(c)
+SQ_TWO_ROW_CUBES
+#undef X
+}  // namespace two_rows
+#undef X_RECURRENCE_DECL
 
-int recurrence_block(int C) {
+int recurrence_block(int C, int shape) {
+    if (shape & ~shape_variants(C)) return 0;
+    if (shape & kShapeTwoRows) {
+        switch (C) {
+#define X(c) case c: return two_rows::block_c##c();
+            SQ_TWO_ROW_CUBES
+#undef X
+            default: return 0;
+        }
+    }
     switch (C) {
 #define X(c) case c: return block_c##c();
         SQ_ALL_CUBES
@@ -3112,27 +3176,54 @@ int recurrence_block(int C) {
     }
 }
 
-hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int nch, int *blocks_per_cu) {
+hipError_t recurrence_occupancy(int C, bool lanczos, bool mixed, int nch, int *blocks_per_cu, int shape) {
+    if (shape & ~shape_variants(C)) return hipErrorInvalidValue;
+    if (shape & kShapeTwoRows) {
+        switch (C) {
+#define X(c) case c: return two_rows::occupancy_c##c(lanczos, mixed, nch, blocks_per_cu, shape);
+            SQ_TWO_ROW_CUBES
+#undef X
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (C) {
-#define X(c) case c: return occupancy_c##c(lanczos, mixed, nch, blocks_per_cu);
+#define X(c) case c: return occupancy_c##c(lanczos, mixed, nch, blocks_per_cu, shape);
         SQ_ALL_CUBES
 #undef X
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_lanczos(const LaunchArgs &a, int C, int nch, int nwg, hipStream_t s) {
+hipError_t launch_lanczos(const LaunchArgs &a, int C, int nch, int nwg, hipStream_t s, int shape) {
+    if (shape & ~shape_variants(C)) return hipErrorInvalidValue;
+    if (shape & kShapeTwoRows) {
+        switch (C) {
+#define X(c) case c: return two_rows::lanczos_c##c(a, nch, nwg, s, shape);
+            SQ_TWO_ROW_CUBES
+#undef X
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (C) {
-#define X(c) case c: return lanczos_c##c(a, nch, nwg, s);
+#define X(c) case c: return lanczos_c##c(a, nch, nwg, s, shape);
         SQ_ALL_CUBES
 #undef X
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_moments(const LaunchArgs &a, int C, int nch, bool mixed, int nwg, hipStream_t s) {
+hipError_t launch_moments(const LaunchArgs &a, int C, int nch, bool mixed, int nwg, hipStream_t s, int shape) {
+    if (shape & ~shape_variants(C)) return hipErrorInvalidValue;
+    if (shape & kShapeTwoRows) {
+        switch (C) {
+#define X(c) case c: return two_rows::moments_c##c(a, nch, mixed, nwg, s, shape);
+            SQ_TWO_ROW_CUBES
+#undef X
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (C) {
-#define X(c) case c: return moments_c##c(a, nch, mixed, nwg, s);
+#define X(c) case c: return moments_c##c(a, nch, mixed, nwg, s, shape);
         SQ_ALL_CUBES
 #undef X
         default: return hipErrorInvalidValue;

@@ -36,7 +36,12 @@ class Options(ct.Structure):
 
 class BatchOptions(ct.Structure):
     _fields_ = [("block_nodes", ct.c_int), ("wg_per_cu", ct.c_int), ("use_graph", ct.c_int),
-                ("bounds_every", ct.c_int), ("reuse_check", ct.c_int)]
+                ("bounds_every", ct.c_int), ("reuse_check", ct.c_int), ("shape", ct.c_int)]
+
+
+# kernel shapes of the batched recurrence launches (bits of BatchOptions.shape)
+SHAPE_TWO_ROWS = 1    # two cube columns per thread (21-27-point cubes)
+SHAPE_TWO_PLANES = 2  # two planes per barrier in the FP64 sweeps (21-31-point cubes)
 
 
 _lib = None
@@ -78,13 +83,14 @@ def load_library():
     lib.sq_batch_step.argtypes = [P, dp, dp, P]
     lib.sq_batch_autotune.argtypes = [P, ct.c_char_p, P]
     lib.sq_batch_tiles.argtypes = [P, ct.POINTER(I), ct.POINTER(I), ct.POINTER(I)]
+    lib.sq_batch_group.argtypes = [P, I, ct.POINTER(I), ct.POINTER(I), ct.POINTER(I), ct.POINTER(I)]
     lib.sq_batch_destroy.argtypes = [P]
     lib.sq_batch_destroy.restype = None
     for name in ("sq_setup", "sq_query", "sq_bind", "sq_update_veff", "sq_spectral_bounds",
                  "sq_set_bounds", "sq_moments", "sq_fermi_level", "sq_density_energy",
                  "sq_density_energy_static", "sq_nl_forces",
                  "sq_batch_create", "sq_batch_query", "sq_batch_bind", "sq_batch_step",
-                 "sq_batch_autotune", "sq_batch_tiles"):
+                 "sq_batch_autotune", "sq_batch_tiles", "sq_batch_group"):
         getattr(lib, name).restype = ct.c_int
     _lib = lib
     return lib
@@ -247,7 +253,7 @@ class Batch:
     of them (persistent work-queue launches; optionally one hipGraph)."""
 
     def __init__(self, snaps, n_electrons, block_nodes=0, wg_per_cu=0, use_graph=True, bounds_every=1,
-                 stream=None, reuse_check=True):
+                 stream=None, reuse_check=True, shape=0):
         import torch
         lib = load_library()
         self.torch = torch
@@ -262,6 +268,7 @@ class Batch:
         opt.block_nodes, opt.wg_per_cu, opt.use_graph = int(block_nodes), int(wg_per_cu), int(bool(use_graph))
         opt.bounds_every = int(bounds_every)
         opt.reuse_check = int(bool(reuse_check))
+        opt.shape = int(shape)
         ctxs = (ct.c_void_p * n)(*[s._ctx for s in self.snaps])
         mom = (ct.c_void_p * n)(*[t.data_ptr() for t in self.moments])
         rho = (ct.c_void_p * n)(*[t.data_ptr() for t in self.rho])
@@ -299,6 +306,17 @@ class Batch:
         b, w, k = ct.c_int(), ct.c_int(), ct.c_int()
         _check(_lib.sq_batch_tiles(self._b, ct.byref(b), ct.byref(w), ct.byref(k)))
         return {"block_nodes": b.value, "wg_per_cu": w.value, "n_items": k.value}
+
+    def groups(self):
+        """Launch groups: [(cube side, projector chains, shape bits), ...]."""
+        n = ct.c_int()
+        _lib.sq_batch_group(self._b, -1, None, None, None, ct.byref(n))
+        out = []
+        for i in range(n.value):
+            c, k, s = ct.c_int(), ct.c_int(), ct.c_int()
+            _check(_lib.sq_batch_group(self._b, i, ct.byref(c), ct.byref(k), ct.byref(s), None))
+            out.append((c.value, k.value, s.value))
+        return out
 
     def __del__(self):
         if getattr(self, "_b", None) and _lib is not None:

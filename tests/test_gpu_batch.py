@@ -124,9 +124,63 @@ def test_batch_mixed_precision():
         assert abs(e[i][3] - wl.n_electrons) < 1e-9 * wl.n_electrons
 
 
-def test_batch_autotune_and_cache(tmp_path):
+def _shape_cells(precision="fp64"):
+    """Cells whose regions have the alternative kernel shapes: 21- and
+    27-point cubes (two rows, two planes) and a 29-point cube (two planes)."""
+    return [
+        W.fcc_workload("s0_al4_c21", 1, 8.0, 0.1, 31, 0.5, 5.0, 24, 1.0, precision=precision),
+        W.fcc_workload("s1_al4_c27", 1, 8.0, 0.1, 32, 0.5, 6.5, 16, 1.0, precision=precision),
+        W.fcc_workload("s2_al4_c29", 1, 8.0, 0.15, 33, 0.5, 7.0, 16, 1.0, precision=precision),
+    ]
+
+
+def _shape_bits(cube):
+    """Kernel shapes a cube side has (SHAPE_TWO_ROWS: 21-27, SHAPE_TWO_PLANES: 21-31)."""
     sq = _sq()
-    wls = _small_ensemble()[:3]
+    return (sq.SHAPE_TWO_ROWS if 21 <= cube <= 27 else 0) | (sq.SHAPE_TWO_PLANES if 21 <= cube <= 31 else 0)
+
+
+@pytest.mark.parametrize("precision,shape", [("fp64", 1), ("fp64", 2), ("fp64", 3), ("mixed", 3)])
+def test_batch_kernel_shapes(precision, shape):
+    """Every kernel shape against the single-snapshot path (default shape) and,
+    on two sampled nodes per cell, against the FP64 oracle."""
+    sq = _sq()
+    wls = _shape_cells(precision)
+    print(f"case kernel shape {shape} {precision}", flush=True)
+    snaps = _snaps(wls)
+    ref = _single(snaps, wls)
+    b = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=False, shape=shape)
+    groups = b.groups()
+    assert sorted(c for c, _, _ in groups) == [21, 27, 29]
+    for c, _, s in groups:
+        assert s == shape & _shape_bits(c), (c, s)
+    mu, e = b.step()
+    if precision == "fp64":
+        _compare(b, mu, e, ref, wls)
+    else:
+        for i, wl in enumerate(wls):
+            rho1 = ref[i][2]
+            assert np.abs(_np(b.rho[i]) - rho1).max() < 1e-7 * rho1.max(), wl.name
+            assert abs(e[i][3] - wl.n_electrons) < 1e-9 * wl.n_electrons
+    rng = np.random.default_rng(11)
+    for i, (wl, g) in enumerate(zip(wls, snaps)):
+        nodes = rng.choice(g.nd, 2, replace=False)
+        o = oracle.Oracle.from_workload(wl, veff=wl.veff())
+        lo, hi = o.bounds(nodes)
+        mom_ref = o.moments(lo, hi, nodes=nodes)
+        rho_ref, _ = o.density_energy(lo, hi, mom_ref, mu[i])
+        r = _np(b.rho[i])
+        err = np.abs(r[nodes] - rho_ref).max() / r.max()
+        print(f"  {wl.name}: sampled rho rel err {err:.2e}", flush=True)
+        assert err < (1e-10 if precision == "fp64" else 1e-5)
+
+
+def test_batch_autotune_and_cache(tmp_path):
+    """The tuner picks a tile (block_nodes x wg_per_cu) and, per launch group,
+    a kernel shape among those its cube side has; the choice is cached and a
+    second batch of the same signature reads it back."""
+    sq = _sq()
+    wls = _small_ensemble()[:3] + _shape_cells()[:2]
     print("case autotune", flush=True)
     snaps = _snaps(wls)
     ref = _single(snaps, wls)
@@ -134,16 +188,25 @@ def test_batch_autotune_and_cache(tmp_path):
     b = sq.Batch(snaps, [wl.n_electrons for wl in wls])
     t = b.autotune(cache)
     assert t["block_nodes"] in (8, 32, 128) and t["n_items"] > 0
+    groups = b.groups()
+    for c, _, s in groups:
+        assert s & ~_shape_bits(c) == 0, (c, s)
     data = json.load(open(cache))
     assert len(data) == 1
     entry = next(iter(data.values()))
     assert entry["block_nodes"] == t["block_nodes"] and entry["wg_per_cu"] == t["wg_per_cu"]
+    # one shape entry per group that has alternatives: cubes 21 and 27
+    assert sorted((c, k, s) for c, k, s in entry["shapes"]) == sorted(
+        (c, k, s) for c, k, s in groups if _shape_bits(c))
+    assert sorted(c for c, _, _ in entry["shapes"]) == [21, 27]
+    print(f"  tiles {t}, groups {groups}", flush=True)
     mu, e = b.step()
     _compare(b, mu, e, ref, wls)
     # a second batch of the same shapes reads the cache
     b2 = sq.Batch(snaps, [wl.n_electrons for wl in wls])
     t2 = b2.autotune(cache)
     assert t2["block_nodes"] == t["block_nodes"] and t2["wg_per_cu"] == t["wg_per_cu"]
+    assert b2.groups() == groups
     assert len(json.load(open(cache))) == 1
 
 
