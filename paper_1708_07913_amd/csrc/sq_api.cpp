@@ -730,7 +730,10 @@ int batch_layout(sq_batch *b) {
 }
 
 // Autotuner cache: a flat JSON object
-// {"key": {"block_nodes": B, "wg_per_cu": W, "shapes": [[C, nch, bits], ...], "ms": T}, ...}.
+// {"key": {"block_nodes": B, "wg_per_cu": W, "shapes": [[C, nch, bits], ...],
+//          "shape_ms": [[C, nch, t0, t1, t2, t3], ...], "ms": T}, ...}
+// where t_s is the sample time (ms) of shape bits s for that group, -1 where
+// its cube side lacks the shape (shape_ms is informative; lookups ignore it).
 std::string tune_key(const sq_batch *b) {
     std::vector<std::string> parts;
     for (const auto &g : b->groups) {
@@ -747,6 +750,7 @@ std::string tune_key(const sq_batch *b) {
 
 struct TunedShape {
     int C, nch, shape;
+    double ms[4];
 };
 
 bool cache_lookup(const char *path, const std::string &key, int *block, int *wg, std::vector<TunedShape> *shapes) {
@@ -772,7 +776,7 @@ bool cache_lookup(const char *path, const std::string &key, int *block, int *wg,
         while (i < text.size() && (text[i] == ' ' || text[i] == ',' || text[i] == '\n')) ++i;
         if (i >= text.size()) return false;
         if (text[i] == ']') return true;
-        TunedShape t{};
+        TunedShape t{0, 0, 0, {-1.0, -1.0, -1.0, -1.0}};
         if (text[i] != '[' || std::sscanf(text.c_str() + i, "[%d, %d, %d]", &t.C, &t.nch, &t.shape) != 3) return false;
         shapes->push_back(t);
         i = text.find(']', i);
@@ -796,6 +800,13 @@ void cache_store(const char *path, const std::string &key, int block, int wg, co
     for (size_t i = 0; i < shapes.size(); ++i)
         sh += (i ? ", [" : "[") + std::to_string(shapes[i].C) + ", " + std::to_string(shapes[i].nch) + ", " +
               std::to_string(shapes[i].shape) + "]";
+    sh += "], \"shape_ms\": [";
+    for (size_t i = 0; i < shapes.size(); ++i) {
+        char t[160];
+        std::snprintf(t, sizeof(t), "%s[%d, %d, %.3f, %.3f, %.3f, %.3f]", i ? ", " : "", shapes[i].C, shapes[i].nch,
+                      shapes[i].ms[0], shapes[i].ms[1], shapes[i].ms[2], shapes[i].ms[3]);
+        sh += t;
+    }
     sh += "]";
     char fields[128];
     std::snprintf(fields, sizeof(fields), "\": {\"block_nodes\": %d, \"wg_per_cu\": %d, \"shapes\": ", block, wg);
@@ -1475,7 +1486,7 @@ int sq_batch_autotune(sq_batch *b, const char *cache_path, void *stream) {
                 auto &g = b->groups[size_t(gi)];
                 const int variants = sq::shape_variants(g.C);
                 if (variants == 0 || g.n_items == 0) continue;
-                int best_sh = 0;
+                TunedShape t{g.C, g.nch, 0, {-1.0, -1.0, -1.0, -1.0}};
                 double best_g = 1e300;
                 for (int sh = 0; sh < 4 && !rc; ++sh) {
                     if (sh & ~variants) continue;
@@ -1483,13 +1494,14 @@ int sq_batch_autotune(sq_batch *b, const char *cache_path, void *stream) {
                     float ms = 0.f, ms2 = 0.f;
                     rc = timed(gi, &ms);
                     if (!rc) rc = timed(gi, &ms2);
-                    if (!rc && std::min(ms, ms2) < best_g) {
-                        best_g = std::min(ms, ms2);
-                        best_sh = sh;
+                    t.ms[sh] = std::min(ms, ms2);
+                    if (!rc && t.ms[sh] < best_g) {
+                        best_g = t.ms[sh];
+                        t.shape = sh;
                     }
                 }
-                g.set_shape(best_sh);
-                shapes.push_back({g.C, g.nch, best_sh});
+                g.set_shape(t.shape);
+                shapes.push_back(t);
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);

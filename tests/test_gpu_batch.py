@@ -199,6 +199,12 @@ def test_batch_autotune_and_cache(tmp_path):
     assert sorted((c, k, s) for c, k, s in entry["shapes"]) == sorted(
         (c, k, s) for c, k, s in groups if _shape_bits(c))
     assert sorted(c for c, _, _ in entry["shapes"]) == [21, 27]
+    # the sample time of every shape the group's cube side has; the chosen one is the fastest
+    chosen = {(c, k): s for c, k, s in entry["shapes"]}
+    for c, k, *ms in entry["shape_ms"]:
+        have = [s for s in range(4) if s & ~_shape_bits(c) == 0]
+        assert all((ms[s] >= 0) == (s in have) for s in range(4)), (c, ms)
+        assert ms[chosen[(c, k)]] == min(ms[s] for s in have), (c, ms)
     print(f"  tiles {t}, groups {groups}", flush=True)
     mu, e = b.step()
     _compare(b, mu, e, ref, wls)
