@@ -278,6 +278,18 @@ def test_batch_bounds_reuse_across_veff_update():
         assert abs(mu[i] - mu1) < 1e-11
         assert np.abs(_np(b.rho[i]) - _np(rho1)).max() < 1e-12 * _np(rho1).max()
         assert abs(e[i][3] - wl.n_electrons) < 1e-10 * wl.n_electrons
+    # the reusing pass of the 16^3 snapshot against the oracle at the new
+    # V_eff on the same (reused) bounds
+    wl = wls[0]
+    o = oracle.Oracle.from_workload(wl, veff=0.98 * wl.veff())
+    lmin, lmax = (_np(t) for t in lo_hi[0])
+    mom_ref = o.moments(lmin, lmax)
+    assert np.abs(_np(b.moments[0]) - mom_ref).max() < 1e-12
+    mu_ref, _ = o.fermi_level(lmin, lmax, mom_ref, wl.n_electrons)
+    assert abs(mu[0] - mu_ref) < 1e-10, (mu[0], mu_ref)
+    rho_ref, e_ref = o.density_energy(lmin, lmax, mom_ref, mu[0])
+    assert np.abs(_np(b.rho[0]) - rho_ref).max() < 1e-10 * rho_ref.max()
+    assert np.abs(e[0] - e_ref).max() < 1e-10 * np.abs(e_ref).max(), (e[0], e_ref)
     # bounds injected from outside (here far too tight): not reused
     lo, hi = lo_hi[0]
     mid = 0.5 * (lo + hi)
