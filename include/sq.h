@@ -272,8 +272,8 @@ int sq_batch_tiles(const sq_batch *batch, int *block_nodes, int *wg_per_cu, int 
 
 /* Launch group i of the batch (one per cube side and chain count, 0 <= i <
  * *n_groups): its cube side, projector chains and SQ_SHAPE_* bits.  Any
- * output may be NULL; SQ_EINVAL if i is out of range (n_groups is still
- * written). */
+ * output may be NULL.  i < 0 writes only n_groups; SQ_EINVAL if i >=
+ * n_groups. */
 int sq_batch_group(const sq_batch *batch, int i, int *cube, int *nch, int *shape, int *n_groups);
 
 /* Release host state and the private stream and graph. */

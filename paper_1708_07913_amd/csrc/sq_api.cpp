@@ -1535,7 +1535,8 @@ int sq_batch_tiles(const sq_batch *b, int *block_nodes, int *wg_per_cu, int *n_i
 int sq_batch_group(const sq_batch *b, int i, int *cube, int *nch, int *shape, int *n_groups) {
     if (!b) return fail(SQ_EINVAL, "null batch");
     if (n_groups) *n_groups = int(b->groups.size());
-    if (i < 0 || i >= int(b->groups.size())) return fail(SQ_EINVAL, "launch group index out of range");
+    if (i < 0) return SQ_OK;
+    if (i >= int(b->groups.size())) return fail(SQ_EINVAL, "launch group index out of range");
     const auto &g = b->groups[size_t(i)];
     if (cube) *cube = g.C;
     if (nch) *nch = g.nch;

@@ -310,7 +310,7 @@ class Batch:
     def groups(self):
         """Launch groups: [(cube side, projector chains, shape bits), ...]."""
         n = ct.c_int()
-        _lib.sq_batch_group(self._b, -1, None, None, None, ct.byref(n))
+        _check(_lib.sq_batch_group(self._b, -1, None, None, None, ct.byref(n)))
         out = []
         for i in range(n.value):
             c, k, s = ct.c_int(), ct.c_int(), ct.c_int()

@@ -107,6 +107,29 @@ def test_null_context_calls():
     lib.sq_destroy(None)
 
 
+def test_batch_options_and_null_batch_calls():
+    lib = sq.load_library()
+    o = sq.BatchOptions()
+    lib.sq_batch_default_options(ct.byref(o))
+    assert (o.block_nodes, o.wg_per_cu, o.use_graph, o.bounds_every, o.reuse_check, o.shape) == (0, 0, 1, 1, 1, 0)
+    n = ct.c_int(-1)
+    assert lib.sq_batch_group(None, 0, None, None, None, ct.byref(n)) == -1
+    assert lib.sq_batch_tiles(None, None, None, None) == -1
+    assert lib.sq_batch_query(None, None) == -1
+    # options are validated before any context is looked at (no device call)
+    ctxs = (ct.c_void_p * 1)(None)
+    ptrs = (ct.c_void_p * 1)(1)
+    ne = (ct.c_double * 1)(4.0)
+    b = ct.c_void_p()
+    for field, value, fragment in (("shape", 4, "shape"), ("block_nodes", 4, "block_nodes"),
+                                   ("bounds_every", -1, "invalid batch options")):
+        lib.sq_batch_default_options(ct.byref(o))
+        setattr(o, field, value)
+        rc = lib.sq_batch_create(ct.byref(b), ctxs, 1, ptrs, ptrs, ne, ct.byref(o))
+        assert rc == -1 and fragment in lib.sq_last_error().decode(), (field, lib.sq_last_error())
+        assert not b.value
+
+
 def test_bench_refuses_more_than_one_gpu():
     """The benchmark runs on one GPU: --gpus above 1 exits with a message."""
     import json
