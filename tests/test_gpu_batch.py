@@ -214,6 +214,19 @@ def test_batch_autotune_and_cache(tmp_path):
     assert t2["block_nodes"] == t["block_nodes"] and t2["wg_per_cu"] == t["wg_per_cu"]
     assert b2.groups() == groups
     assert len(json.load(open(cache))) == 1
+    # an entry edited by hand (every shape bit the cubes have, 32 nodes per
+    # item) is applied as read, and the pass keeps its parity
+    data = json.load(open(cache))
+    key = next(iter(data))
+    data[key]["block_nodes"] = 32
+    data[key]["shapes"] = [[c, k, _shape_bits(c)] for c, k, _ in data[key]["shapes"]]
+    json.dump(data, open(cache, "w"))
+    b3 = sq.Batch(snaps, [wl.n_electrons for wl in wls])
+    t3 = b3.autotune(cache)
+    assert t3["block_nodes"] == 32
+    assert all(s == _shape_bits(c) for c, _, s in b3.groups())
+    mu, e = b3.step()
+    _compare(b3, mu, e, ref, wls)
 
 
 def test_batch_ensemble_sampled():
