@@ -3,11 +3,12 @@
 //
 // Recurrence kernels (Lanczos bounds and Chebyshev moments) -- one workgroup
 // per region of influence at a time, persistent over nodes:
-//   * thread (x, y) owns the z-column of the cube; the current vector t^k of
-//     that column lives in VGPRs (z-neighbours of the stencil come from
-//     registers);
+//   * a thread owns one, two or three y-adjacent z-columns of the cube (by
+//     cube side; see Shape); the current vector t^k of those columns lives in
+//     VGPRs (z-neighbours of the stencil come from registers);
 //   * x/y neighbours come from a zero-padded LDS plane of t^k that is rewritten
-//     once per z (double-buffered, one barrier per plane); the zero halo is the
+//     once per z (double-buffered, one barrier per plane, or two planes per
+//     barrier in the kernels built with PPB = 2); the zero halo is the
 //     Dirichlet truncation of Sec. 3.1;
 //   * t^{k-1} streams through a per-workgroup global slot that is read and
 //     overwritten with t^k in the same sweep (two vector passes per step);
@@ -48,7 +49,8 @@ constexpr int NO = kNoMax;
 #define SQ_LANCZOS_AHEAD 1
 #endif
 // Two-row build of the 21-27-point cubes (a second object of this file; its
-// kernels live in namespace sq::two_rows)
+// kernels live in namespace sq::two_rows, opened above when the build defines
+// SQ_TWO_ROWS=1; left undefined, the preprocessor reads it as 0 there)
 #ifndef SQ_TWO_ROWS
 #define SQ_TWO_ROWS 0
 #endif
