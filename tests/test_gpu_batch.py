@@ -175,6 +175,21 @@ def test_batch_kernel_shapes(precision, shape):
         assert err < (1e-10 if precision == "fp64" else 1e-5)
 
 
+def test_batch_shape_bits_ignored_where_absent():
+    """Shape bits a cube side does not have (11-, 15- and streamed 33-point
+    cubes) leave its launches at the default shape."""
+    sq = _sq()
+    wls = _small_ensemble()
+    print("case shape bits on cubes without shapes", flush=True)
+    snaps = _snaps(wls)
+    ref = _single(snaps, wls)
+    b = sq.Batch(snaps, [wl.n_electrons for wl in wls], use_graph=False,
+                 shape=sq.SHAPE_TWO_ROWS | sq.SHAPE_TWO_PLANES)
+    assert all(s == 0 for _, _, s in b.groups()), b.groups()
+    mu, e = b.step()
+    _compare(b, mu, e, ref, wls)
+
+
 def test_batch_autotune_and_cache(tmp_path):
     """The tuner picks a tile (block_nodes x wg_per_cu) and, per launch group,
     a kernel shape among those its cube side has; the choice is cached and a
